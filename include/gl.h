@@ -1,0 +1,209 @@
+/*
+ * gl.h - C ABI of the MI355X lens-likelihood library (libglens.so).
+ *
+ * Batched GIGA-Lens forward model, Gaussian log-likelihood and its gradient, evaluated for
+ * many parameter vectors at once on one GPU (Gu et al. 2022, arXiv:2202.07663), plus a
+ * fixed-budget multi-start fit and a continuous-batching server for streams of systems.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: GL_OK (0) on success, GL_PENDING (1) from gl_poll only, a negative
+ *     GL_E_* code on failure. No C++ exception crosses the ABI. gl_last_error() returns a
+ *     thread-local, human-readable message for the last failure on the calling thread.
+ *   - Device buffers (theta, img, logl, grad) are caller-owned device pointers on the
+ *     current HIP device; they are never freed or retained by the library. Host buffers
+ *     named in descriptors (psf, obs, priors) are copied before the call returns.
+ *   - Compute calls are stream-ordered: `stream` is a hipStream_t (NULL = default stream).
+ *     They enqueue work and return; outputs are valid once the stream is synchronised.
+ *     Calls on one gl_model must be ordered on one stream (the model owns the work space).
+ *   - Parameter vectors theta are FP32, row-major [P][d], physical (constrained) values in
+ *     this order (Sec. 2.1.2, eq. sim-dist; arcsec for lengths, counts/s for intensities):
+ *        mass:       theta_E, [gamma_epl if EPL], eps1, eps2, x, y, [gamma_ext1, gamma_ext2]
+ *        lens light: R, n, eps1, eps2, x, y, I                    (if lens_light)
+ *        source:     R, n, eps1, eps2, x, y, I                    (always)
+ *        shapelets:  beta, c_0 .. c_{M-1}, M = (n+1)(n+2)/2       (if shapelet_nmax >= 0)
+ *     The shapelet centre is the source Sersic centre. d is reported by gl_model_nparams.
+ *   - Non-finite per-particle results (e.g. NaN parameters) are not call failures: that
+ *     particle's log-likelihood is -inf and its gradient row is zero.
+ */
+#ifndef GLENS_GL_H
+#define GLENS_GL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GL_OK = 0,
+  GL_PENDING = 1,
+  GL_E_INVALID = -1,       /* bad argument (null pointer, size, flag, host pointer ...) */
+  GL_E_NOMEM = -2,         /* device allocation failed */
+  GL_E_DEVICE = -3,        /* HIP runtime error */
+  GL_E_BUDGET = -4,        /* request larger than the server's HBM budget */
+  GL_E_NOTFOUND = -5,      /* unknown ticket */
+  GL_E_NUMERIC = -6,       /* fit produced no finite particle */
+  GL_E_UNIMPLEMENTED = -7, /* configuration outside what the kernels support */
+  GL_E_CLOSED = -8         /* server is shutting down */
+};
+
+enum { GL_MASS_SIE = 0, GL_MASS_EPL = 1 };
+
+#define GL_MAX_PARAMS 68   /* EPL + shear + lens light + source + shapelets n_max = 8 */
+#define GL_MAX_NMAX 8
+#define GL_MAX_PSF 31
+#define GL_MAX_IMAGE 128   /* H, W <= 128 */
+#define GL_MAX_KSUPER 4
+
+/*
+ * Lens system description (Sec. 2.1: image grid, mass and light components, noise model,
+ * PSF). Pixel (i, j) (row i, column j) has centre ((j - (W-1)/2) s, (i - (H-1)/2) s) with
+ * s = pixel_scale; each pixel is evaluated on a k_super x k_super sub-grid and averaged
+ * (Sec. 2.1.1, last paragraph), then convolved with the PSF (zero-padded, same size).
+ */
+typedef struct gl_model_desc {
+  int H, W;            /* image rows and columns, 1..GL_MAX_IMAGE */
+  float pixel_scale;   /* arcsec per pixel, > 0 */
+  int k_super;         /* supersampling factor, 1..GL_MAX_KSUPER */
+  int mass;            /* GL_MASS_SIE or GL_MASS_EPL */
+  int shear;           /* 1: external shear (2 parameters), 0: none */
+  int lens_light;      /* 1: elliptical Sersic lens light (7 parameters), 0: none */
+  int shapelet_nmax;   /* -1: no shapelets; 0..GL_MAX_NMAX: Cartesian shapelets to n_max */
+  int psf_size;        /* K, odd, 1..GL_MAX_PSF */
+  const float* psf;    /* host, K*K row-major, used as given (not renormalised); copied */
+  const float* obs;    /* host, H*W row-major observed image (counts/s); copied; may be
+                          NULL for a model used only by gl_simulate */
+  float sigma_bkg;     /* background noise sigma (counts/s), >= 0 */
+  float t_exp;         /* exposure time (s), > 0 */
+  float gain;          /* G (e-/count), > 0 */
+} gl_model_desc;
+
+typedef struct gl_model gl_model;
+
+/* Validate `desc`, copy the PSF and observed image to the current device and return an
+ * opaque handle in *out. GL_E_INVALID for a bad field, GL_E_UNIMPLEMENTED for sizes
+ * beyond the GL_MAX_* limits, GL_E_NOMEM / GL_E_DEVICE on runtime failure. */
+int gl_model_create(const gl_model_desc* desc, gl_model** out);
+
+/* Free the model and its device work space (synchronises the device first). NULL is a
+ * no-op. */
+int gl_model_destroy(gl_model* model);
+
+/* Number d of parameters per vector for this model (layout above). */
+int gl_model_nparams(const gl_model* model, int* d);
+
+/* Noiseless model image I_model(x, y; Theta) (Sec. 2.1.1: deflect, ray trace, source plus
+ * lens light, k x k mean, PSF) for P parameter vectors.
+ *   theta: device, [P][d] FP32.  img: device, [P][H][W] FP32 (written).
+ * P = 0 is a no-op. */
+int gl_simulate(gl_model* model, const float* theta, int P, float* img, void* stream);
+
+/* Log-likelihood of eq. model-def (Sec. 2.1.2) for P parameter vectors:
+ *   log L = -1/2 sum_pixels [ (I_obs - I_model)^2 / s2 + log(2 pi s2) ],
+ *   s2 = sigma_bkg^2 + max(I_model, 0) / (G t_exp).
+ * Per-pixel terms in FP32, summed in FP64.
+ *   theta: device [P][d] FP32.  logl: device [P] FP64 (written).
+ * GL_E_INVALID if the model has no observed image. */
+int gl_loglik(gl_model* model, const float* theta, int P, double* logl, void* stream);
+
+/* log L (as gl_loglik) and its gradient d log L / d Theta in physical parameters
+ * (Sec. 2.2: the paper obtains it by automatic differentiation; here a hand-written
+ * adjoint of every step). grad: device [P][d] FP32 (written). */
+int gl_loglik_grad(gl_model* model, const float* theta, int P, double* logl, float* grad,
+                   void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Priors, bijectors and the fixed-budget multi-start fit (Sec. 2.2 bijectors and
+ * Jacobian-corrected posterior; Sec. 2.3 multi-start gradient descent with Adam).
+ * The bijector follows the prior family: NORMAL -> identity, LOGNORMAL -> exp,
+ * TRUNCNORMAL and UNIFORM on (lo, hi) -> lo + (hi - lo) / (1 + exp(-z)).
+ * ------------------------------------------------------------------------------------- */
+enum { GL_PRIOR_NORMAL = 0, GL_PRIOR_LOGNORMAL = 1, GL_PRIOR_TRUNCNORMAL = 2,
+       GL_PRIOR_UNIFORM = 3 };
+
+typedef struct gl_prior {
+  int family;      /* GL_PRIOR_* */
+  float mu, sigma; /* NORMAL / TRUNCNORMAL: mean, sd; LOGNORMAL: mean, sd of log(theta) */
+  float lo, hi;    /* TRUNCNORMAL / UNIFORM support, lo < hi */
+} gl_prior;
+
+typedef struct gl_fit_opts {
+  int P;                  /* particles (multi-start samples), >= 1 */
+  int K;                  /* Adam steps, >= 1 */
+  float lr0, lr1;         /* learning rate, linear from lr0 to lr1 over the K steps */
+  float beta1, beta2, eps;/* Adam constants (0.9, 0.999, 1e-8 if all three are 0) */
+  uint64_t seed;          /* starts are drawn from the prior with a counter-based RNG */
+  const gl_prior* priors; /* host, d entries, copied */
+} gl_fit_opts;
+
+typedef struct gl_fit_result {
+  int status;             /* GL_OK, or GL_E_NUMERIC / GL_E_DEVICE ... for this request */
+  int d;                  /* number of parameters */
+  int best;               /* index of the best particle */
+  float theta_best[GL_MAX_PARAMS];
+  double logl_best;       /* log L at theta_best */
+  double logpost_best;    /* log L + log p + log|J| at the best particle's z */
+  double chi2nu;          /* chi^2 / (H W - d) at theta_best */
+  uint64_t t_submit, t_admit, t_done;  /* ns, CLOCK_MONOTONIC (server results only) */
+} gl_fit_result;
+
+/* One multi-start fit of one system, run to completion on `stream` (blocking): P starts
+ * from the prior, K Adam steps on f = -(log L + log p + log|J|) in unconstrained space,
+ * then the best particle by log posterior at its final position. */
+int gl_fit(gl_model* model, const gl_fit_opts* opts, gl_fit_result* out, void* stream);
+
+/* Lower-level fit state, for stepping and inspection. Buffers are device, owned by the
+ * state. gl_fit_state_z returns the device pointer of z[P][d]; m and v likewise. */
+typedef struct gl_fit_state gl_fit_state;
+int gl_fit_state_create(gl_model* model, const gl_fit_opts* opts, gl_fit_state** out,
+                        void* stream);
+int gl_fit_state_destroy(gl_fit_state* st);
+/* Run `n` Adam steps (continuing the schedule). */
+int gl_fit_state_step(gl_fit_state* st, int n, void* stream);
+/* Device pointers to the state arrays ([P][d] FP32) and the step counter. */
+int gl_fit_state_arrays(gl_fit_state* st, float** z, float** m, float** v, int* step);
+/* Evaluate log L at the current z, pick the best particle, fill *out (blocking). */
+int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Continuous-batching server: systems of mixed sizes and component sets are admitted as
+ * slots and HBM budget free up; each tick advances every active system by
+ * steps_per_tick Adam steps, with the systems of one kernel configuration sharing one
+ * launch per kernel.
+ * ------------------------------------------------------------------------------------- */
+typedef struct gl_server_opts {
+  size_t hbm_budget_bytes; /* device memory the active systems may hold (state + scratch) */
+  int max_systems;         /* active-system slots */
+  int steps_per_tick;      /* Adam steps per system per tick, >= 1 */
+} gl_server_opts;
+
+typedef struct gl_server gl_server;
+
+/* Start the scheduler thread on the current device. */
+int gl_server_create(const gl_server_opts* opts, gl_server** out);
+/* Stop accepting work, finish active systems, join the thread, free everything. */
+int gl_server_destroy(gl_server* s);
+/* Queue one fit request (desc and opts are copied; non-blocking). GL_E_BUDGET if the
+ * request alone exceeds the HBM budget, GL_E_INVALID for a bad request. */
+int gl_submit(gl_server* s, const gl_model_desc* desc, const gl_fit_opts* opts,
+              uint64_t* ticket);
+/* GL_PENDING while the request is queued or running; GL_OK with *out filled once done
+ * (the ticket is then released); GL_E_NOTFOUND for an unknown ticket. */
+int gl_poll(gl_server* s, uint64_t ticket, gl_fit_result* out);
+
+typedef struct gl_server_stats {
+  uint64_t submitted, admitted, completed, ticks;
+  size_t hbm_in_use, hbm_peak;
+  int active, queued;
+} gl_server_stats;
+int gl_server_get_stats(gl_server* s, gl_server_stats* out);
+
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char* gl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLENS_GL_H */

@@ -1,0 +1,160 @@
+"""MI355X-native batched lens likelihood and adjoint (GIGA-Lens, arXiv:2202.07663).
+
+Thin Python layer over libglens.so (C ABI in include/gl.h). PyTorch supplies device memory
+and streams; every step of the lens model runs in the library's HIP kernels.
+
+    m = Model(H=60, W=60, pixel_scale=0.065, k_super=2, mass="epl", lens_light=True,
+              shapelet_nmax=6, psf=psf, obs=obs, sigma_bkg=0.1, t_exp=1000.0)
+    logl = m.loglik(theta)                 # theta: cuda float32 [P, d] -> float64 [P]
+    logl, grad = m.loglik_grad(theta)      # grad: float32 [P, d]
+    logl = LogLik.apply(theta, m)          # differentiable (backward uses the adjoint)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GlError, check, lib
+
+__all__ = ["Model", "LogLik", "GlError", "param_names", "nparams"]
+
+
+def nparams(mass: str, shear: bool, lens_light: bool, shapelet_nmax: int) -> int:
+    return ((6 if mass == "epl" else 5) + (2 if shear else 0) + (7 if lens_light else 0) + 7
+            + (0 if shapelet_nmax < 0 else 1 + (shapelet_nmax + 1) * (shapelet_nmax + 2) // 2))
+
+
+def param_names(mass: str, shear: bool, lens_light: bool, shapelet_nmax: int) -> list:
+    n = ["theta_E"] + (["gamma"] if mass == "epl" else []) + ["e1", "e2", "x", "y"]
+    n += ["gamma1", "gamma2"] if shear else []
+    n += ["l_R", "l_n", "l_e1", "l_e2", "l_x", "l_y", "l_I"] if lens_light else []
+    n += ["s_R", "s_n", "s_e1", "s_e2", "s_x", "s_y", "s_I"]
+    if shapelet_nmax >= 0:
+        n += ["beta"] + [f"c{i}" for i in range(nparams("sie", False, False, shapelet_nmax) - 13)]
+    return n
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def make_desc(H, W, pixel_scale, k_super, mass, shear, lens_light, shapelet_nmax, psf, obs,
+              sigma_bkg, t_exp, gain):
+    """Build a gl_model_desc; returns (desc, keepalive arrays)."""
+    psf = _f32(psf)
+    keep = [psf]
+    obs_p = None
+    if obs is not None:
+        obs = _f32(obs)
+        assert obs.shape == (H, W), "obs must be H x W"
+        keep.append(obs)
+        obs_p = obs.ctypes.data_as(_lib._fp)
+    assert psf.ndim == 2 and psf.shape[0] == psf.shape[1], "psf must be K x K"
+    d = _lib.ModelDesc(H, W, pixel_scale, k_super,
+                       _lib.GL_MASS_EPL if mass == "epl" else _lib.GL_MASS_SIE,
+                       int(shear), int(lens_light), shapelet_nmax, psf.shape[0],
+                       psf.ctypes.data_as(_lib._fp), obs_p, sigma_bkg, t_exp, gain)
+    return d, keep
+
+
+class Model:
+    """One lens system (image grid, components, PSF, observed image, noise model) on the
+    current GPU. Calls are ordered on the current torch stream."""
+
+    def __init__(self, H: int, W: int, pixel_scale: float, k_super: int, mass: str = "epl",
+                 shear: bool = True, lens_light: bool = True, shapelet_nmax: int = -1,
+                 psf=None, obs=None, sigma_bkg: float = 0.1, t_exp: float = 1000.0,
+                 gain: float = 1.0):
+        assert mass in ("sie", "epl")
+        self.H, self.W, self.k_super = H, W, k_super
+        self.mass, self.shear, self.lens_light, self.nmax = mass, shear, lens_light, shapelet_nmax
+        self.has_obs = obs is not None
+        desc, keep = make_desc(H, W, pixel_scale, k_super, mass, shear, lens_light,
+                               shapelet_nmax, psf, obs, sigma_bkg, t_exp, gain)
+        self._desc, self._keep = desc, keep
+        h = ctypes.c_void_p()
+        check(lib().gl_model_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        d = ctypes.c_int()
+        check(lib().gl_model_nparams(self._h, ctypes.byref(d)))
+        self.d = d.value
+        self.names = param_names(mass, shear, lens_light, shapelet_nmax)
+        assert len(self.names) == self.d
+
+    @classmethod
+    def from_spec(cls, spec, obs=None):
+        """Build from a ``synth.Spec``-like object."""
+        return cls(spec.H, spec.W, spec.pix, spec.k, "epl" if spec.epl else "sie", spec.shear,
+                   spec.lens_light, spec.nmax, spec.psf, obs, spec.sigma_bkg, spec.t_exp,
+                   spec.gain)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _theta(self, theta: torch.Tensor) -> torch.Tensor:
+        if not (isinstance(theta, torch.Tensor) and theta.is_cuda):
+            raise TypeError("theta must be a CUDA tensor")
+        if theta.dtype != torch.float32 or theta.dim() != 2 or theta.shape[1] != self.d:
+            raise ValueError(f"theta must be float32 [P, {self.d}]")
+        return theta.contiguous()
+
+    def simulate(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
+        theta = self._theta(theta)
+        P = theta.shape[0]
+        img = torch.empty((P, self.H, self.W), dtype=torch.float32, device=theta.device)
+        check(lib().gl_simulate(self._h, theta.data_ptr(), P, img.data_ptr(), _stream_ptr(stream)))
+        return img
+
+    def loglik(self, theta: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        theta = self._theta(theta)
+        P = theta.shape[0]
+        ll = out if out is not None else torch.empty(P, dtype=torch.float64, device=theta.device)
+        check(lib().gl_loglik(self._h, theta.data_ptr(), P, ll.data_ptr(), _stream_ptr(stream)))
+        return ll
+
+    def loglik_grad(self, theta: torch.Tensor, out=None, stream=None):
+        theta = self._theta(theta)
+        P = theta.shape[0]
+        if out is None:
+            ll = torch.empty(P, dtype=torch.float64, device=theta.device)
+            g = torch.empty((P, self.d), dtype=torch.float32, device=theta.device)
+        else:
+            ll, g = out
+        check(lib().gl_loglik_grad(self._h, theta.data_ptr(), P, ll.data_ptr(), g.data_ptr(),
+                                   _stream_ptr(stream)))
+        return ll, g
+
+
+class LogLik(torch.autograd.Function):
+    """log L(theta) as a differentiable function of theta [P, d] (float32, CUDA).
+
+    forward runs gl_loglik_grad once and saves the gradient; backward returns
+    grad_out[:, None] * grad (log L is one scalar per parameter vector, so this is the exact
+    vector-Jacobian product)."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, model: Model):
+        ll, g = model.loglik_grad(theta.detach())
+        ctx.save_for_backward(g)
+        return ll
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out.to(g.dtype)[:, None] * g), None

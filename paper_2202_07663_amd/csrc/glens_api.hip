@@ -1,0 +1,443 @@
+// C ABI: models, gl_simulate, gl_loglik, gl_loglik_grad, errors; kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "glens_host.h"
+#include "glens_kernels.h"
+
+namespace glens {
+
+// ------------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------------
+static thread_local std::string t_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+void clear_error() { t_err.clear(); }
+
+#define GL_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
+                       #call, hipGetErrorString(e_));                                    \
+  } while (0)
+
+int check_device_ptr(const void* p, const char* name) {
+  if (!p) return set_error(GL_E_INVALID, "%s is NULL", name);
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GL_E_INVALID, "%s is not a device pointer", name);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return set_error(GL_E_INVALID, "%s is not a device pointer", name);
+  return GL_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// descriptors
+// ------------------------------------------------------------------------------------------
+int nparams(int mass, int shear, int lens_light, int nmax) {
+  return (mass == GL_MASS_EPL ? 6 : 5) + (shear ? 2 : 0) + (lens_light ? 7 : 0) + 7 +
+         (nmax >= 0 ? 1 + (nmax + 1) * (nmax + 2) / 2 : 0);
+}
+
+int validate_desc(const gl_model_desc* d, ModelCfg* c) {
+  if (!d) return set_error(GL_E_INVALID, "desc is NULL");
+  if (d->H < 1 || d->W < 1) return set_error(GL_E_INVALID, "image size %dx%d", d->H, d->W);
+  if (d->H > GL_MAX_IMAGE || d->W > GL_MAX_IMAGE)
+    return set_error(GL_E_UNIMPLEMENTED, "image size %dx%d above %d", d->H, d->W, GL_MAX_IMAGE);
+  if (!(d->pixel_scale > 0.f) || !std::isfinite(d->pixel_scale))
+    return set_error(GL_E_INVALID, "pixel_scale must be > 0");
+  if (d->k_super < 1) return set_error(GL_E_INVALID, "k_super must be >= 1");
+  if (d->k_super > GL_MAX_KSUPER)
+    return set_error(GL_E_UNIMPLEMENTED, "k_super above %d", GL_MAX_KSUPER);
+  if (d->mass != GL_MASS_SIE && d->mass != GL_MASS_EPL)
+    return set_error(GL_E_INVALID, "mass must be GL_MASS_SIE or GL_MASS_EPL");
+  if (d->shear != 0 && d->shear != 1) return set_error(GL_E_INVALID, "shear must be 0 or 1");
+  if (d->lens_light != 0 && d->lens_light != 1)
+    return set_error(GL_E_INVALID, "lens_light must be 0 or 1");
+  if (d->shapelet_nmax < -1) return set_error(GL_E_INVALID, "shapelet_nmax must be >= -1");
+  if (d->shapelet_nmax > GL_MAX_NMAX)
+    return set_error(GL_E_UNIMPLEMENTED, "shapelet_nmax above %d", GL_MAX_NMAX);
+  if (d->psf_size < 1 || d->psf_size % 2 == 0)
+    return set_error(GL_E_INVALID, "psf_size must be odd and >= 1");
+  if (d->psf_size > GL_MAX_PSF)
+    return set_error(GL_E_UNIMPLEMENTED, "psf_size above %d", GL_MAX_PSF);
+  if (!d->psf) return set_error(GL_E_INVALID, "psf is NULL");
+  for (int i = 0; i < d->psf_size * d->psf_size; ++i)
+    if (!std::isfinite(d->psf[i])) return set_error(GL_E_INVALID, "psf has non-finite values");
+  if (!(d->sigma_bkg >= 0.f) || !std::isfinite(d->sigma_bkg))
+    return set_error(GL_E_INVALID, "sigma_bkg must be >= 0");
+  if (!(d->t_exp > 0.f) || !std::isfinite(d->t_exp)) return set_error(GL_E_INVALID, "t_exp must be > 0");
+  if (!(d->gain > 0.f) || !std::isfinite(d->gain)) return set_error(GL_E_INVALID, "gain must be > 0");
+  if (d->obs)
+    for (int i = 0; i < d->H * d->W; ++i)
+      if (!std::isfinite(d->obs[i])) return set_error(GL_E_INVALID, "obs has non-finite values");
+  if (d->sigma_bkg == 0.f && d->obs == nullptr) {
+    // fine: simulate-only
+  }
+  c->H = d->H;
+  c->W = d->W;
+  c->k = d->k_super;
+  c->K = d->psf_size;
+  c->pix = d->pixel_scale;
+  c->mass = d->mass;
+  c->shear = d->shear;
+  c->lens_light = d->lens_light;
+  c->nmax = d->shapelet_nmax;
+  c->d = nparams(d->mass, d->shear, d->lens_light, d->shapelet_nmax);
+  c->sigma_bkg = d->sigma_bkg;
+  c->t_exp = d->t_exp;
+  c->gain = d->gain;
+  return GL_OK;
+}
+
+int system_upload(const gl_model_desc* d, const ModelCfg& cfg, SystemData& sd) {
+  sd.cfg = cfg;
+  const int KK = cfg.K * cfg.K, HW = cfg.H * cfg.W;
+  std::vector<float> flip(KK);
+  for (int a = 0; a < cfg.K; ++a)
+    for (int b = 0; b < cfg.K; ++b) flip[a * cfg.K + b] = d->psf[(cfg.K - 1 - a) * cfg.K + (cfg.K - 1 - b)];
+  GL_HIP(hipMalloc(&sd.psf, sizeof(float) * KK));
+  GL_HIP(hipMalloc(&sd.psf_flip, sizeof(float) * KK));
+  GL_HIP(hipMemcpy(sd.psf, d->psf, sizeof(float) * KK, hipMemcpyHostToDevice));
+  GL_HIP(hipMemcpy(sd.psf_flip, flip.data(), sizeof(float) * KK, hipMemcpyHostToDevice));
+  sd.has_obs = d->obs != nullptr;
+  GL_HIP(hipMalloc(&sd.obs, sizeof(float) * HW));
+  if (d->obs) GL_HIP(hipMemcpy(sd.obs, d->obs, sizeof(float) * HW, hipMemcpyHostToDevice));
+  else GL_HIP(hipMemset(sd.obs, 0, sizeof(float) * HW));
+  sd.bytes = sizeof(float) * (2 * KK + HW);
+  return GL_OK;
+}
+
+void system_free(SystemData& sd) {
+  if (sd.psf) (void)hipFree(sd.psf);
+  if (sd.psf_flip) (void)hipFree(sd.psf_flip);
+  if (sd.obs) (void)hipFree(sd.obs);
+  sd.psf = sd.psf_flip = sd.obs = nullptr;
+}
+
+int choose_tiles(int P, int HW) {
+  // aim at >= 2048 workgroups per launch (8 per CU); never fewer than 256 pixels a tile
+  const int want = (2048 + P - 1) / std::max(P, 1);
+  const int maxt = std::max(1, (HW + kSubThreads - 1) / kSubThreads);
+  return std::max(1, std::min(want, maxt));
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit) {
+  size_t b = align256(sizeof(PConst) * P) + 2 * align256(sizeof(float) * (size_t)P * HW) +
+             align256(sizeof(double) * (size_t)P * tiles * kNAcc);
+  if (fit) b += align256(sizeof(double) * P) + 2 * align256(sizeof(float) * (size_t)P * d);
+  return b;
+}
+
+void workspace_free(Workspace& ws) {
+  if (ws.pc) (void)hipFree(ws.pc);
+  ws = Workspace();
+}
+
+int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit) {
+  if (ws.pc && P <= ws.cap_P && tiles <= ws.cap_tiles && HW == ws.HW && (!fit || ws.logl))
+    return GL_OK;
+  const int cP = std::max(P, ws.cap_P), cT = std::max(tiles, ws.cap_tiles);
+  if (ws.pc) {
+    GL_HIP(hipDeviceSynchronize());
+    workspace_free(ws);
+  }
+  const size_t bytes = workspace_bytes(cP, cT, HW, d, fit);
+  char* base = nullptr;
+  GL_HIP(hipMalloc(&base, bytes));
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align256(b);
+    return p;
+  };
+  ws.pc = reinterpret_cast<PConst*>(take(sizeof(PConst) * cP));
+  ws.m0 = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
+  ws.sbar = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
+  ws.acc = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * cT * kNAcc));
+  if (fit) {
+    ws.logl = reinterpret_cast<double*>(take(sizeof(double) * cP));
+    ws.grad = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
+    ws.theta = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
+  }
+  ws.cap_P = cP;
+  ws.cap_tiles = cT;
+  ws.HW = HW;
+  ws.bytes = bytes;
+  return GL_OK;
+}
+
+SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
+  const ModelCfg& c = sd.cfg;
+  SysDesc s;
+  std::memset(&s, 0, sizeof(s));
+  s.H = c.H;
+  s.W = c.W;
+  s.k = c.k;
+  s.K = c.K;
+  const double pix = c.pix;
+  s.dxs = pix / c.k;
+  s.x0 = -0.5 * (c.W - 1) * pix + (0.5 / c.k - 0.5) * pix;
+  s.y0 = -0.5 * (c.H - 1) * pix + (0.5 / c.k - 0.5) * pix;
+  s.inv_k2 = 1.0f / float(c.k * c.k);
+  s.s2b = c.sigma_bkg * c.sigma_bkg;
+  s.inv_gt = 1.0f / (c.gain * c.t_exp);
+  s.mass = c.mass;
+  s.shear = c.shear;
+  s.lens_light = c.lens_light;
+  s.nmax = c.nmax;
+  s.d = c.d;
+  s.P = P;
+  s.tiles = tiles;
+  const int HW = c.H * c.W;
+  s.pix_per_tile = (HW + tiles - 1) / tiles;
+  s.obs = sd.obs;
+  s.psf = sd.psf;
+  s.psf_flip = sd.psf_flip;
+  s.pc = ws.pc;
+  s.m0 = ws.m0;
+  s.sbar = ws.sbar;
+  s.acc = ws.acc;
+  return s;
+}
+
+int subpix_key(const ModelCfg& c) { return c.mass * 16 + (c.nmax + 1); }
+
+// ------------------------------------------------------------------------------------------
+// kernel dispatch
+// ------------------------------------------------------------------------------------------
+using GroupKernel = void (*)(Group);
+
+template <int MASS, int NMAX>
+struct SubKernels {
+  static constexpr GroupKernel fwd = subpix_fwd_kernel<MASS, NMAX>;
+  static constexpr GroupKernel adj = subpix_adj_kernel<MASS, NMAX>;
+};
+
+template <int MASS, int... N>
+static void fill_sub(GroupKernel* f, GroupKernel* a, std::integer_sequence<int, N...>) {
+  ((f[MASS * 16 + N] = SubKernels<MASS, N - 1>::fwd), ...);
+  ((a[MASS * 16 + N] = SubKernels<MASS, N - 1>::adj), ...);
+}
+
+struct SubTable {
+  GroupKernel fwd[32] = {};
+  GroupKernel adj[32] = {};
+  SubTable() {
+    fill_sub<0>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+    fill_sub<1>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+  }
+};
+static const SubTable& sub_table() {
+  static SubTable t;
+  return t;
+}
+
+template <int... I>
+static void fill_conv(GroupKernel* f, std::integer_sequence<int, I...>) {
+  ((f[I] = conv_kernel<2 * I + 1>), ...);
+}
+struct ConvTable {
+  GroupKernel k[(GL_MAX_PSF + 1) / 2] = {};
+  ConvTable() { fill_conv(k, std::make_integer_sequence<int, (GL_MAX_PSF + 1) / 2>{}); }
+};
+static const ConvTable& conv_table() {
+  static ConvTable t;
+  return t;
+}
+
+static int launch(GroupKernel k, int blocks, int threads, size_t lds, const Group& g,
+                  hipStream_t st) {
+  if (blocks <= 0) return GL_OK;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, st, g);
+  GL_HIP(hipGetLastError());
+  return GL_OK;
+}
+
+int launch_prologue(const Group& g, hipStream_t st) {
+  return launch(prologue_kernel, g.block0[g.nsys], 64, 0, g, st);
+}
+int launch_subpix_fwd(int key, const Group& g, hipStream_t st) {
+  return launch(sub_table().fwd[key], g.block0[g.nsys], kSubThreads, 0, g, st);
+}
+int launch_subpix_adj(int key, const Group& g, hipStream_t st) {
+  return launch(sub_table().adj[key], g.block0[g.nsys], kSubThreads, 0, g, st);
+}
+int launch_finalize(const Group& g, hipStream_t st) {
+  return launch(finalize_kernel, g.block0[g.nsys], 64, 0, g, st);
+}
+
+size_t conv_lds_bytes(int H, int W, int K, int mode) {
+  const int nstrip = (H + kConvRows - 1) / kConvRows;
+  const size_t np = size_t(nstrip * kConvRows + K - 1) * (W + K - 1);
+  return sizeof(float) * np * (mode == 2 ? 2 : 1);
+}
+
+int launch_conv(int K, const Group& g, size_t lds, hipStream_t st) {
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    for (auto k : conv_table().k) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+      if (e != hipSuccess) attr_err = e;
+    }
+  });
+  if (attr_err != hipSuccess && lds > 64 * 1024)
+    return set_error(GL_E_DEVICE, "cannot raise the LDS limit: %s", hipGetErrorString(attr_err));
+  return launch(conv_table().k[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st);
+}
+
+// Block offsets of each system for one stage.
+template <class F>
+static void set_blocks(Group& g, F per_sys) {
+  int b = 0;
+  for (int i = 0; i < g.nsys; ++i) {
+    g.block0[i] = b;
+    b += per_sys(g.sys[i]);
+  }
+  g.block0[g.nsys] = b;
+}
+
+int run_group(Group& g, int key, int K, int mode, hipStream_t st) {
+  int rc;
+  set_blocks(g, blocks_prologue);
+  if ((rc = launch_prologue(g, st))) return rc;
+  set_blocks(g, blocks_subpix);
+  if ((rc = launch_subpix_fwd(key, g, st))) return rc;
+  size_t lds = 0;
+  for (int i = 0; i < g.nsys; ++i) {
+    g.sys[i].mode = mode;
+    lds = std::max(lds, conv_lds_bytes(g.sys[i].H, g.sys[i].W, K, mode));
+  }
+  set_blocks(g, blocks_conv);
+  if ((rc = launch_conv(K, g, lds, st))) return rc;
+  if (mode != 2) return GL_OK;
+  set_blocks(g, blocks_subpix);
+  if ((rc = launch_subpix_adj(key, g, st))) return rc;
+  set_blocks(g, blocks_prologue);
+  return launch_finalize(g, st);
+}
+
+}  // namespace glens
+
+using namespace glens;
+
+// ==========================================================================================
+// C ABI
+// ==========================================================================================
+extern "C" {
+
+const char* gl_last_error(void) { return t_err.c_str(); }
+
+int gl_model_create(const gl_model_desc* desc, gl_model** out) {
+  clear_error();
+  if (!out) return set_error(GL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  ModelCfg cfg;
+  int rc = validate_desc(desc, &cfg);
+  if (rc) return rc;
+  gl_model* m = new (std::nothrow) gl_model();
+  if (!m) return set_error(GL_E_NOMEM, "host allocation failed");
+  GL_HIP(hipGetDevice(&m->device));
+  rc = system_upload(desc, cfg, m->sys);
+  if (rc) {
+    system_free(m->sys);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return GL_OK;
+}
+
+int gl_model_destroy(gl_model* m) {
+  clear_error();
+  if (!m) return GL_OK;
+  (void)hipDeviceSynchronize();
+  workspace_free(m->ws);
+  system_free(m->sys);
+  delete m;
+  return GL_OK;
+}
+
+int gl_model_nparams(const gl_model* m, int* d) {
+  clear_error();
+  if (!m || !d) return set_error(GL_E_INVALID, "NULL argument");
+  *d = m->sys.cfg.d;
+  return GL_OK;
+}
+
+static int run_model(gl_model* m, const float* theta, int P, int mode, float* img, double* logl,
+                     float* grad, hipStream_t st) {
+  const ModelCfg& c = m->sys.cfg;
+  const int HW = c.H * c.W;
+  const int tiles = choose_tiles(P, HW);
+  int rc = workspace_reserve(m->ws, P, tiles, HW, c.d, false);
+  if (rc) return rc;
+  Group g;
+  std::memset(&g, 0, sizeof(g));
+  g.nsys = 1;
+  g.sys[0] = make_sys(m->sys, m->ws, P, tiles);
+  g.sys[0].theta = theta;
+  g.sys[0].img = img;
+  g.sys[0].logl = logl;
+  g.sys[0].grad = grad;
+  return run_group(g, subpix_key(c), c.K, mode, st);
+}
+
+static int common_checks(gl_model* m, const float* theta, int P) {
+  if (!m) return set_error(GL_E_INVALID, "model is NULL");
+  if (P < 0) return set_error(GL_E_INVALID, "P must be >= 0");
+  if (P == 0) return GL_OK;
+  return check_device_ptr(theta, "theta");
+}
+
+int gl_simulate(gl_model* m, const float* theta, int P, float* img, void* stream) {
+  clear_error();
+  int rc = common_checks(m, theta, P);
+  if (rc || P == 0) return rc;
+  if ((rc = check_device_ptr(img, "img"))) return rc;
+  return run_model(m, theta, P, 0, img, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int gl_loglik(gl_model* m, const float* theta, int P, double* logl, void* stream) {
+  clear_error();
+  int rc = common_checks(m, theta, P);
+  if (rc || P == 0) return rc;
+  if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
+  if ((rc = check_device_ptr(logl, "logl"))) return rc;
+  return run_model(m, theta, P, 1, nullptr, logl, nullptr, (hipStream_t)stream);
+}
+
+int gl_loglik_grad(gl_model* m, const float* theta, int P, double* logl, float* grad,
+                   void* stream) {
+  clear_error();
+  int rc = common_checks(m, theta, P);
+  if (rc || P == 0) return rc;
+  if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
+  if ((rc = check_device_ptr(logl, "logl"))) return rc;
+  if ((rc = check_device_ptr(grad, "grad"))) return rc;
+  return run_model(m, theta, P, 2, nullptr, logl, grad, (hipStream_t)stream);
+}
+
+}  // extern "C"

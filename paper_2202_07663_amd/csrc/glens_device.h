@@ -1,0 +1,462 @@
+// Per-particle decode and per-sub-pixel forward / adjoint math of the lens model.
+//
+// Forward model (Gu et al. 2022, Sec. 2.1.1): deflection by an elliptical power law (EPL,
+// deflection through the Gauss hypergeometric series of Tessore & Metcalf 2015) or its
+// slope-2 case the SIE (closed form), plus external shear; ray trace beta = x - alpha;
+// elliptical Sersic source plus Cartesian shapelets at beta; elliptical Sersic lens light
+// at x.
+//
+// Everything is written in complex image-plane variables that are smooth in the
+// eccentricities (eps1, eps2), so the gradient has no 0/0 at a round lens:
+//   z = (x - x_c) + i (y - y_c),  eps = eps1 + i eps2,  w = z - eps conj(z),
+//   B = theta_E sqrt(1 - |eps|^2),  X = conj(eps) w^2 / |w|^2,
+//   alpha = B^t |w|^-t w S_t(X),  S_t(X) = sum_n c_n(t) (-X)^n,
+//   c_0 = 1,  c_n = c_{n-1} (2n - 2 + t) / (2n + 2 - t),  t = gamma_epl - 1.
+// This is the paper's (q, phi) form rewritten: with q = (1-|eps|)/(1+|eps|),
+// q x_l + i y_l = ((1+q)/2) e^{-i phi} w, the elliptical radius R = |w| / (1 + |eps|), the
+// prefactor 2b/(1+q) (b/R)^(t-1) = B^t |w|^(1-t) and (1-q)/(1+q) e^{-2i phi} = conj(eps).
+// For t = 1 the series sums to S_1(X) = atan(sqrt X) / sqrt X, the SIE closed form.
+//
+// Precision: sub-pixel positions, the deflection and the ray trace run in FP64 (on CDNA4 a
+// double FMA issues at the rate of an unpacked float FMA), so the source offset
+// beta - x_s keeps full FP32 relative precision even where the source has a cusp; the light
+// profiles and all derivative terms run in FP32 on offsets from their centres.
+//
+// Sersic light uses the rotation-free quadratic form of the elliptical radius,
+//   q x_l^2 + y_l^2 / q = [(1+|e|^2-2e1) dx^2 - 4 e2 dx dy + (1+|e|^2+2e1) dy^2] / (1-|e|^2),
+// which is the same quantity without the position angle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "glens_types.h"
+
+#define GL_HD __host__ __device__ __forceinline__
+
+namespace glens {
+
+constexpr float kInvSqrtPi = 0.56418958354775628f;
+
+// ------------------------------------------------------------------------------------------
+// Per-particle decode (prologue). Double precision: it runs once per particle.
+// ------------------------------------------------------------------------------------------
+
+// Rescale |eps| onto eps_max when above it; returns the clamp Jacobian (symmetric).
+GL_HD void clamp_eps(double e1, double e2, double emax, double& c1, double& c2, double& j11,
+                     double& j12, double& j22) {
+  const double r = sqrt(e1 * e1 + e2 * e2);
+  if (r > emax) {
+    const double s = emax / r, u1 = e1 / r, u2 = e2 / r;
+    c1 = e1 * s;
+    c2 = e2 * s;
+    j11 = s * (1.0 - u1 * u1);
+    j12 = -s * u1 * u2;
+    j22 = s * (1.0 - u2 * u2);
+  } else {
+    c1 = e1;
+    c2 = e2;
+    j11 = 1.0;
+    j12 = 0.0;
+    j22 = 1.0;
+  }
+}
+
+GL_HD void decode_light(const float* th, LightC& L) {
+  const double re = th[0], n = th[1];
+  double e1, e2, j11, j12, j22;
+  clamp_eps(th[2], th[3], kLightEpsMax, e1, e2, j11, j12, j22);
+  const double ee = e1 * e1 + e2 * e2, den = 1.0 / (1.0 - ee);
+  L.i0 = th[6];
+  L.qa = float((1.0 + ee - 2.0 * e1) * den);
+  L.qb = float(-4.0 * e2 * den);
+  L.qc = float((1.0 + ee + 2.0 * e1) * den);
+  L.inv2n = float(0.5 / n);
+  L.lnre_n = float(log(re) / n);
+  L.bn = float(1.9992 * n - 0.3271);
+  L.n = float(n);
+  L.re = float(re);
+  L.e1 = float(e1);
+  L.e2 = float(e2);
+  L.inv1me2 = float(den);
+  L.j11 = float(j11);
+  L.j12 = float(j12);
+  L.j22 = float(j22);
+}
+
+// Decode one parameter vector (layout of gl.h) into the per-particle constants.
+GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light, int nmax,
+                           PConst& c) {
+  int p = 0;
+  const double theta_e = th[p++];
+  const double t = (mass == 1) ? double(th[p++]) - 1.0 : 1.0;
+  double e1, e2, j11, j12, j22;
+  clamp_eps(th[p], th[p + 1], kMassEpsMax, e1, e2, j11, j12, j22);
+  p += 2;
+  c.xc = th[p++];
+  c.yc = th[p++];
+  if (shear) {
+    c.g1 = th[p++];
+    c.g2 = th[p++];
+  } else {
+    c.g1 = 0.0;
+    c.g2 = 0.0;
+  }
+  const double ee = e1 * e1 + e2 * e2, eabs = sqrt(ee);
+  const double B = theta_e * sqrt(1.0 - ee);
+  c.t = t;
+  c.e1 = e1;
+  c.e2 = e2;
+  c.tlnb = t * log(B);
+  c.bmass = B;
+  c.w2floor = 1e-12 * (1.0 + eabs) * (1.0 + eabs);
+  c.epsabs = eabs;
+  c.theta_e = float(theta_e);
+  c.tf = float(t);
+  c.e1f = float(e1);
+  c.e2f = float(e2);
+  c.lnb = float(log(B));
+  c.tfac = float(t / (2.0 * (1.0 - ee)));
+  c.mj11 = float(j11);
+  c.mj12 = float(j12);
+  c.mj22 = float(j22);
+  // series: terms until the tail bound |eps|^N / (1 - |eps|) drops below the tolerance
+  int nt = 1;
+  if (eabs > 1e-30) {
+    nt = int(ceil(log(kSeriesTol * (1.0 - eabs)) / log(eabs)));
+    nt = nt < 1 ? 1 : (nt > kMaxTerms ? kMaxTerms : nt);
+  }
+  c.nterms = nt;
+  double cn = 1.0, dsum = 0.0;
+  for (int n = 0; n < kMaxTerms; ++n) {
+    if (n > 0) {
+      const double a = 2.0 * n - 2.0 + t, b = 2.0 * n + 2.0 - t;
+      cn *= a / b;
+      dsum += 1.0 / a + 1.0 / b;
+    }
+    c.c[n] = n < nt ? cn : 0.0;
+    c.dc[n] = n < nt ? float(cn * dsum) : 0.f;
+  }
+  // SIE closed form: s = sqrt(conj(eps)), S_1(X) = atan(s u) / (s u), u = w / |w|
+  c.sie_closed = (mass == 0 && eabs >= kSieClosedMin) ? 1 : 0;
+  if (c.sie_closed) {
+    const double ang = -0.5 * atan2(e2, e1), rs = sqrt(eabs);
+    c.sr = rs * cos(ang);
+    c.si = rs * sin(ang);
+  } else {
+    c.sr = c.si = 0.0;
+  }
+  c.lxs = c.lys = 0.0;
+  if (lens_light) {
+    decode_light(th + p, c.lens);
+    c.lxs = th[p + 4];
+    c.lys = th[p + 5];
+    p += 7;
+  }
+  decode_light(th + p, c.src);
+  c.sxs = th[p + 4];
+  c.sys = th[p + 5];
+  p += 7;
+  if (nmax >= 0) {
+    const double beta = th[p++];
+    c.beta = float(beta);
+    c.inv_beta = float(1.0 / beta);
+    const int M = (nmax + 1) * (nmax + 2) / 2;
+    for (int k = 0; k < M; ++k) c.shp[k] = float(double(th[p + k]) / beta * 0.56418958354775628);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sub-pixel math
+// ------------------------------------------------------------------------------------------
+
+struct Cx {
+  float r, i;
+};
+GL_HD Cx cmul(Cx a, Cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+GL_HD Cx cadd(Cx a, Cx b) { return {a.r + b.r, a.i + b.i}; }
+GL_HD Cx csub(Cx a, Cx b) { return {a.r - b.r, a.i - b.i}; }
+GL_HD Cx cscale(Cx a, float s) { return {a.r * s, a.i * s}; }
+GL_HD Cx cconj(Cx a) { return {a.r, -a.i}; }
+GL_HD Cx cmuli(Cx a) { return {-a.i, a.r}; }  // i a
+GL_HD float cdot(Cx g, Cx v) { return g.r * v.r + g.i * v.i; }  // real dot product
+
+// Ray trace of one sub-pixel; the FP32 fields are kept for the adjoint.
+struct MassState {
+  float sdx, sdy;     // beta - x_s (source offset)
+  Cx z, w, u2, X;     // z, w, w^2/|w|^2, X = conj(eps) u2
+  float lnw2;         // ln |w|^2 (floored)
+  float A;            // B^t |w|^-t
+  Cx S, SX, St;       // S_t(X), dS/dX, dS/dt
+  Cx alpha;
+  int floored;        // |w|^2 hit the floor
+};
+
+// EPL / SIE deflection plus shear at image position (x, y); beta = x - alpha - alpha_ext.
+// ADJ: also dS/dX and dS/dt (FP32).
+template <int MASS, bool ADJ>
+GL_HD void mass_eval(const PConst& c, double x, double y, MassState& m) {
+  const double zr = x - c.xc, zi = y - c.yc;
+  const double e1 = c.e1, e2 = c.e2;
+  const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
+  double w2 = wr * wr + wi * wi;
+  m.floored = w2 < c.w2floor;
+  w2 = m.floored ? c.w2floor : w2;
+  const double inv_w2 = 1.0 / w2;
+  const double u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0 * wr * wi * inv_w2;
+  const double Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
+  const double lnw2 = log(w2);
+  double Sr, Si, A;
+  if (MASS == 0 && c.sie_closed) {
+    // S_1(X) = atan(zeta) / zeta, zeta = s w / |w|; atan of |zeta| < 1 in closed form
+    const double rinv = sqrt(inv_w2);
+    const double ur = wr * rinv, ui = wi * rinv;
+    const double a = c.sr * ur - c.si * ui, b = c.sr * ui + c.si * ur;
+    const double aa = a * a;
+    const double atr = 0.5 * atan(2.0 * a / (1.0 - c.epsabs));
+    const double ati = 0.25 * log(((1.0 + b) * (1.0 + b) + aa) / ((1.0 - b) * (1.0 - b) + aa));
+    const double ie = 1.0 / c.epsabs;  // S = atan(zeta) conj(zeta) / |eps|
+    Sr = (atr * a + ati * b) * ie;
+    Si = (ati * a - atr * b) * ie;
+    A = c.bmass * rinv;
+    if (ADJ) {
+      // S_X = (1/(1+X) - S) / (2X), in double: cancels for small |X|
+      const double opr = 1.0 + Xr, opi = Xi, d = 1.0 / (opr * opr + opi * opi);
+      const double nr = opr * d - Sr, ni = -opi * d - Si;
+      const double dx = 0.5 / (Xr * Xr + Xi * Xi);
+      m.SX = {float((nr * Xr + ni * Xi) * dx), float((ni * Xr - nr * Xi) * dx)};
+      m.St = {0.f, 0.f};
+    }
+  } else {
+    const double yr = -Xr, yi = -Xi;
+    const float yrf = float(yr), yif = float(yi);
+    double sr = 0.0, si = 0.0;
+    float dr = 0.f, di = 0.f, tr = 0.f, ti = 0.f;
+    const int nt = c.nterms;
+    for (int n = nt - 1; n >= 0; --n) {
+      if (ADJ) {
+        const float ndr = dr * yrf - di * yif + float(sr);
+        const float ndi = dr * yif + di * yrf + float(si);
+        dr = ndr;
+        di = ndi;
+        if (MASS == 1) {
+          const float ntr = tr * yrf - ti * yif + c.dc[n];
+          const float nti = tr * yif + ti * yrf;
+          tr = ntr;
+          ti = nti;
+        }
+      }
+      const double nsr = sr * yr - si * yi + c.c[n];
+      const double nsi = sr * yi + si * yr;
+      sr = nsr;
+      si = nsi;
+    }
+    Sr = sr;
+    Si = si;
+    if (ADJ) {
+      m.SX = {-dr, -di};  // d/dX = -d/dy
+      m.St = {tr, ti};
+    }
+    A = exp(c.tlnb - 0.5 * c.t * lnw2);
+  }
+  const double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
+  // beta - x_s = x - alpha - alpha_ext - x_s
+  m.sdx = float(x - ar - (c.g1 * x + c.g2 * y) - c.sxs);
+  m.sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
+  if (ADJ) {
+    m.z = {float(zr), float(zi)};
+    m.w = {float(wr), float(wi)};
+    m.u2 = {float(u2r), float(u2i)};
+    m.X = {float(Xr), float(Xi)};
+    m.lnw2 = float(lnw2);
+    m.A = float(A);
+    m.S = {float(Sr), float(Si)};
+    m.alpha = {float(ar), float(ai)};
+  }
+}
+
+// Adds the mass-parameter terms of g . d(beta)/d(theta) to acc, with g = d s / d beta
+// (already weighted by the pixel adjoint). beta = x - alpha - alpha_ext.
+template <int MASS>
+GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, Cx g, float* acc) {
+  const float t = c.tf;
+  // Wirtinger derivatives of alpha w.r.t. w and conj(w) (eps fixed)
+  const Cx XSX = cmul(m.X, m.SX);
+  Cx P1 = cadd(cscale(m.S, 1.0f - 0.5f * t), XSX);
+  Cx P2 = csub(cscale(m.S, -0.5f * t), XSX);
+  if (m.floored) {  // |w|^2 frozen at the floor: X = conj(eps) w^2 / floor
+    P1 = cadd(m.S, cscale(XSX, 2.0f));
+    P2 = {0.f, 0.f};
+  }
+  const Cx aw = cscale(P1, m.A);
+  const Cx awb = cscale(cmul(m.u2, P2), m.A);
+  const Cx eps = {c.e1f, c.e2f}, epsb = {c.e1f, -c.e2f};
+  // d alpha / d z = aw - conj(eps) awb ; d alpha / d conj(z) = awb - eps aw
+  const Cx az = csub(aw, cmul(epsb, awb));
+  const Cx azb = csub(awb, cmul(eps, aw));
+  const Cx ax = cadd(az, azb);            // d alpha / d x
+  const Cx ay = cmuli(csub(az, azb));     // d alpha / d y
+  // d alpha / d eps and d alpha / d conj(eps)
+  const Cx zb = cconj(m.z);
+  const Cx ae = csub(cscale(cmul(m.alpha, epsb), -c.tfac), cmul(aw, zb));
+  Cx aeb = csub(cscale(cmul(m.alpha, eps), -c.tfac), cmul(awb, m.z));
+  aeb = cadd(aeb, cscale(cmul(cmul(m.w, m.u2), m.SX), m.A));
+  const Cx ae1 = cadd(ae, aeb);
+  const Cx ae2 = cmuli(csub(ae, aeb));
+  acc[A_M_ALPHA] += cdot(g, m.alpha);
+  if (MASS == 1) {
+    // d alpha / d t = alpha (ln B - ln|w|^2 / 2) + A w S_t
+    Cx at = cscale(m.alpha, c.lnb - 0.5f * m.lnw2);
+    at = cadd(at, cscale(cmul(m.w, m.St), m.A));
+    acc[A_M_T] += cdot(g, at);
+  }
+  acc[A_M_E1] += cdot(g, ae1);
+  acc[A_M_E2] += cdot(g, ae2);
+  acc[A_M_X] += cdot(g, ax);
+  acc[A_M_Y] += cdot(g, ay);
+  acc[A_M_G1] += g.r * x - g.i * y;
+  acc[A_M_G2] += g.r * y + g.i * x;
+}
+
+// Elliptical Sersic intensity at offset (dx, dy) from its centre.
+struct LightEval {
+  float I, E, rho, lnrho, IQ, Q;
+  int floored;
+};
+
+GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
+  float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
+  q = q < kR2Floor ? kR2Floor : q;
+  const float rho = expf(L.inv2n * logf(q) - L.lnre_n);
+  return L.i0 * expf(L.bn * (1.0f - rho));
+}
+
+// Intensity plus the accumulator terms (weight sb) and d I / d(dx, dy).
+GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc, float& gdx,
+                       float& gdy) {
+  float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
+  const bool fl = q < kR2Floor;
+  q = fl ? kR2Floor : q;
+  const float lnrho = L.inv2n * logf(q) - L.lnre_n;
+  const float rho = expf(lnrho);
+  const float E = expf(L.bn * (1.0f - rho));
+  const float I = L.i0 * E;
+  const float IQ = fl ? 0.0f : -I * L.bn * rho * L.inv2n / q;
+  gdx = IQ * (2.0f * L.qa * dx + L.qb * dy);
+  gdy = IQ * (L.qb * dx + 2.0f * L.qc * dy);
+  const float sI = sb * I, sIQ = sb * IQ, r2q = dx * dx + dy * dy + q;
+  acc[L_E] += sb * E;
+  acc[L_RHO] += sI * rho;
+  acc[L_RHO1] += sI * (rho - 1.0f);
+  acc[L_RHOLN] += sI * rho * lnrho;
+  acc[L_Q1] += sIQ * (L.e1 * r2q - dx * dx + dy * dy);
+  acc[L_Q2] += sIQ * (L.e2 * r2q - 2.0f * dx * dy);
+  return I;
+}
+
+// Normalised Hermite polynomials h_n = phi_n / phi_0 (phi_n the Hermite functions):
+// h_0 = 1, h_1 = sqrt(2) u, h_{n+1} = sqrt(2/(n+1)) u h_n - sqrt(n/(n+1)) h_{n-1}.
+template <int NMAX>
+GL_HD void hermite(float u, float* h) {
+  h[0] = 1.0f;
+  if (NMAX >= 1) h[1] = 1.41421356237f * u;
+#pragma unroll
+  for (int n = 1; n < NMAX; ++n)
+    h[n + 1] = sqrtf(2.0f / (n + 1)) * u * h[n] - sqrtf(float(n) / (n + 1)) * h[n - 1];
+}
+
+// Shapelet intensity at offset (sdx, sdy) from the source centre: G(u, v) sum_k c'_k h_n1(u) h_n2(v), c'_k = c_k / (beta sqrt(pi)),
+// ordered n = 0..NMAX, n1 = n..0, n2 = n - n1.
+template <int NMAX>
+GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
+  const float u = sdx * c.inv_beta, v = sdy * c.inv_beta;
+  float hu[NMAX + 1], hv[NMAX + 1];
+  hermite<NMAX>(u, hu);
+  hermite<NMAX>(v, hv);
+  float U = 0.f;
+  int k = 0;
+#pragma unroll
+  for (int n = 0; n <= NMAX; ++n)
+#pragma unroll
+    for (int n1 = n; n1 >= 0; --n1, ++k) U += c.shp[k] * hu[n1] * hv[n - n1];
+  return expf(-0.5f * (u * u + v * v)) * U;
+}
+
+// Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y).
+template <int NMAX>
+GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float* acc, float& gbx,
+                         float& gby) {
+  const float ib = c.inv_beta;
+  const float u = sdx * ib, v = sdy * ib;
+  float hu[NMAX + 1], hv[NMAX + 1];
+  hermite<NMAX>(u, hu);
+  hermite<NMAX>(v, hv);
+  const float G = expf(-0.5f * (u * u + v * v));
+  const float sg = sb * G;
+  float U = 0.f, Uu = 0.f, Uv = 0.f;
+  int k = 0;
+#pragma unroll
+  for (int n = 0; n <= NMAX; ++n) {
+#pragma unroll
+    for (int n1 = n; n1 >= 0; --n1, ++k) {
+      const int n2 = n - n1;
+      const float ck = c.shp[k];
+      const float hh = hu[n1] * hv[n2];
+      U += ck * hh;
+      if (n1 > 0) Uu += ck * sqrtf(2.0f * n1) * hu[n1 - 1] * hv[n2];
+      if (n2 > 0) Uv += ck * sqrtf(2.0f * n2) * hu[n1] * hv[n2 - 1];
+      acc[A_SHP_C + k] += sg * hh;
+    }
+  }
+  const float I = G * U;
+  const float Iu = G * (Uu - u * U), Iv = G * (Uv - v * U);
+  acc[A_SHP_BETA] += sb * (-I - u * Iu - v * Iv) * ib;
+  gbx = Iu * ib;
+  gby = Iv * ib;
+  return I;
+}
+
+// ------------------------------------------------------------------------------------------
+// Accumulators -> d logL / d theta in the parameter order of gl.h. Returns d.
+// ------------------------------------------------------------------------------------------
+GL_HD void light_grad(const LightC& L, const double* a, float* g) {
+  g[0] = float(a[L_RHO] * L.bn / (double(L.n) * L.re));                 // R_eff
+  g[1] = float(-1.9992 * a[L_RHO1] + L.bn / double(L.n) * a[L_RHOLN]);  // n
+  const double ge1 = 2.0 * L.inv1me2 * a[L_Q1], ge2 = 2.0 * L.inv1me2 * a[L_Q2];
+  g[2] = float(L.j11 * ge1 + L.j12 * ge2);                               // eps1
+  g[3] = float(L.j12 * ge1 + L.j22 * ge2);                               // eps2
+  g[4] = float(-a[L_DX]);                                                // x
+  g[5] = float(-a[L_DY]);                                                // y
+  g[6] = float(a[L_E]);                                                  // I0
+}
+
+GL_HD int map_gradient(const PConst& c, const double* a, int mass, int shear, int lens_light,
+                       int nmax, float* gr) {
+  int j = 0;
+  gr[j++] = float(-double(c.t) / c.theta_e * a[A_M_ALPHA]);
+  if (mass == 1) gr[j++] = float(-a[A_M_T]);
+  gr[j++] = float(-(c.mj11 * a[A_M_E1] + c.mj12 * a[A_M_E2]));
+  gr[j++] = float(-(c.mj12 * a[A_M_E1] + c.mj22 * a[A_M_E2]));
+  gr[j++] = float(a[A_M_X]);
+  gr[j++] = float(a[A_M_Y]);
+  if (shear) {
+    gr[j++] = float(-a[A_M_G1]);
+    gr[j++] = float(-a[A_M_G2]);
+  }
+  if (lens_light) {
+    light_grad(c.lens, a + A_LENS, gr + j);
+    j += 7;
+  }
+  light_grad(c.src, a + A_SRC, gr + j);
+  j += 7;
+  if (nmax >= 0) {
+    gr[j++] = float(a[A_SHP_BETA]);
+    const int M = (nmax + 1) * (nmax + 2) / 2;
+    const double f = double(c.inv_beta) * kInvSqrtPi;
+    for (int q = 0; q < M; ++q) gr[j++] = float(a[A_SHP_C + q] * f);
+  }
+  return j;
+}
+
+}  // namespace glens

@@ -1,0 +1,91 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/gl.h"
+#include "glens_types.h"
+
+namespace glens {
+
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// Validated copy of a model descriptor (host pointers dropped).
+struct ModelCfg {
+  int H, W, k, K;
+  float pix;
+  int mass, shear, lens_light, nmax, d;
+  float sigma_bkg, t_exp, gain;
+};
+
+int validate_desc(const gl_model_desc* desc, ModelCfg* cfg);
+int nparams(int mass, int shear, int lens_light, int nmax);
+
+// Device work space of one system for P particles.
+struct Workspace {
+  int cap_P = 0, cap_tiles = 0, HW = 0;
+  PConst* pc = nullptr;
+  float* m0 = nullptr;
+  float* sbar = nullptr;
+  double* acc = nullptr;
+  double* logl = nullptr;  // internal log L (fits)
+  float* grad = nullptr;   // internal gradient (fits)
+  float* theta = nullptr;  // internal theta (fits)
+  size_t bytes = 0;
+};
+size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit_buffers);
+int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit_buffers);
+void workspace_free(Workspace& ws);
+
+// Number of sub-pixel work tiles per particle for P particles of an H x W image.
+int choose_tiles(int P, int HW);
+
+// Device copy of the fixed inputs of one system.
+struct SystemData {
+  ModelCfg cfg;
+  float* psf = nullptr;
+  float* psf_flip = nullptr;
+  float* obs = nullptr;
+  int has_obs = 0;
+  size_t bytes = 0;
+};
+int system_upload(const gl_model_desc* desc, const ModelCfg& cfg, SystemData& sd);
+void system_free(SystemData& sd);
+
+// Fill the launch descriptor of one system.
+SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles);
+
+// Kernel configuration key of a system (systems with equal keys share launches).
+int subpix_key(const ModelCfg& c);  // mass * 16 + (nmax + 1)
+
+// Launch stages over a group of systems (all with the same key / PSF size).
+int launch_prologue(const Group& g, hipStream_t st);
+int launch_subpix_fwd(int key, const Group& g, hipStream_t st);
+int launch_conv(int K, const Group& g, size_t lds_bytes, hipStream_t st);
+int launch_subpix_adj(int key, const Group& g, hipStream_t st);
+int launch_finalize(const Group& g, hipStream_t st);
+size_t conv_lds_bytes(int H, int W, int K, int mode);
+
+// Block counts of one system per stage.
+inline int blocks_prologue(const SysDesc& s) { return (s.P + 63) / 64; }
+inline int blocks_subpix(const SysDesc& s) { return s.P * s.tiles; }
+inline int blocks_conv(const SysDesc& s) { return s.P; }
+
+// Run the forward (+adjoint) pipeline for a group of systems sharing key and PSF size.
+// mode: 0 image, 1 log L, 2 log L + gradient.
+int run_group(Group& g, int key, int K, int mode, hipStream_t st);
+
+int check_device_ptr(const void* p, const char* name);
+
+}  // namespace glens
+
+struct gl_model {
+  int device = 0;
+  glens::SystemData sys;
+  glens::Workspace ws;
+};

@@ -1,0 +1,120 @@
+// Internal data layout shared by the host launchers and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace glens {
+
+constexpr int kMaxTerms = 48;      // EPL series terms (|eps| <= 0.6 needs 47 at the tolerance)
+constexpr int kMaxNmax = 8;        // shapelet order
+constexpr int kMaxShp = (kMaxNmax + 1) * (kMaxNmax + 2) / 2;  // 45
+constexpr int kMaxParams = 68;
+constexpr int kNAcc = 72;          // adjoint accumulator slots per (particle, tile)
+constexpr float kR2Floor = 1e-12f; // arcsec^2 floor on elliptical radii
+constexpr float kMassEpsMax = 0.6f;
+constexpr float kLightEpsMax = 0.9f;
+constexpr float kSieClosedMin = 0.1f;  // SIE closed form for |eps| >= this, series below
+constexpr double kSeriesTol = 1e-10;   // EPL series truncation, relative (far below FP32)
+
+// Accumulator slots of the adjoint (per particle, summed over sub-pixels).
+enum AccSlot {
+  A_M_ALPHA = 0,  // sum g.alpha                      -> theta_E (and SIE)
+  A_M_T = 1,      // sum g.(d alpha / d t)             -> gamma_epl
+  A_M_E1 = 2, A_M_E2 = 3,   // sum g.(d alpha / d eps_k) (clamped eps)
+  A_M_X = 4, A_M_Y = 5,     // sum g.(d alpha / d x), g.(d alpha / d y)
+  A_M_G1 = 6, A_M_G2 = 7,   // sum g.(x, -y), g.(y, x)
+  A_LENS = 8,     // 8 slots, see LightSlot
+  A_SRC = 16,     // 8 slots; the centre slots also collect the shapelet beta-gradient
+  A_SHP_BETA = 24,
+  A_SHP_C = 25,   // kMaxShp slots
+};
+enum LightSlot { L_E = 0, L_RHO = 1, L_RHO1 = 2, L_RHOLN = 3, L_Q1 = 4, L_Q2 = 5, L_DX = 6, L_DY = 7 };
+static_assert(A_SHP_C + kMaxShp <= kNAcc, "accumulator slots");
+
+// Elliptical Sersic constants of one particle.
+struct LightC {
+  float qa, qb, qc;    // R^2 = qa dx^2 + qb dx dy + qc dy^2
+  float inv2n;         // 1 / (2n)
+  float lnre_n;        // ln(R_eff) / n
+  float bn, i0;        // b_n = 1.9992 n - 0.3271, I0
+  float n, re;         // Sersic index, R_eff
+  float e1, e2;        // clamped eccentricities
+  float inv1me2;       // 1 / (1 - |eps|^2)
+  float j11, j12, j22; // d eps_clamped / d eps (symmetric)
+};
+
+// Per-particle constants written by the prologue and read (uniformly) by every sub-pixel
+// lane of that particle.
+struct PConst {
+  int nterms;          // EPL / SIE series terms
+  int sie_closed;      // SIE: 1 = closed form, 0 = series
+  // FP64 part: positions and the deflection are evaluated in double precision, because the
+  // ray-traced source offset beta - x_s must be accurate to far below the FP32 resolution
+  // of arcsecond-scale coordinates near a cuspy source.
+  double t;            // gamma - 1
+  double e1, e2;       // clamped mass eccentricities
+  double xc, yc, g1, g2;
+  double tlnb;         // t ln B, B = theta_E sqrt(1 - |eps|^2)
+  double bmass;        // B
+  double w2floor;      // R^2 floor expressed on |w|^2: 1e-12 (1 + |eps|)^2
+  double sr, si;       // SIE closed form: s = sqrt(conj(eps))
+  double epsabs;
+  double c[kMaxTerms]; // series coefficients c_n(t)
+  double sxs, sys;     // source centre
+  double lxs, lys;     // lens-light centre
+  // FP32 part
+  float theta_e, tf;   // Einstein radius, t
+  float e1f, e2f;
+  float lnb;
+  float tfac;          // t / (2 (1 - |eps|^2))
+  float mj11, mj12, mj22;
+  LightC lens, src;
+  float beta, inv_beta;
+  float shp[kMaxShp];  // c_k / (beta sqrt(pi))
+  float dc[kMaxTerms]; // d c_n / dt
+};
+
+// Prior / bijector of one parameter (the fit).
+struct Prior {
+  int family;          // GL_PRIOR_*
+  float mu, sigma, lo, hi;
+  float logc;          // additive constant of log p (normalisation)
+};
+
+// One lens system as seen by one launch.
+struct SysDesc {
+  int H, W, k, K;
+  double x0, y0, dxs;  // first sub-pixel centre and sub-pixel pitch (arcsec)
+  float inv_k2;
+  float s2b, inv_gt;   // sigma_bkg^2, 1 / (G t_exp)
+  int mass, shear, lens_light, nmax, d;
+  int P;
+  int tiles;           // sub-pixel work tiles per particle
+  int pix_per_tile;
+  int mode;            // conv kernel: 0 image, 1 log L, 2 log L + adjoint seed
+  const float* obs;
+  const float* psf;      // K*K
+  const float* psf_flip; // K*K, flipped in both axes
+  const float* theta;    // [P][d] physical parameters, or null if z is given
+  const float* z;        // [P][d] unconstrained parameters (fit), or null
+  const Prior* prior;    // [d] (fit)
+  float* theta_out;      // [P][d] physical parameters written when z is given
+  PConst* pc;            // [P]
+  float* m0;             // [P][H][W] downsampled image before the PSF
+  float* img;            // [P][H][W] model image (mode 0)
+  float* sbar;           // [P][H][W] d logL / d (sub-pixel brightness) per pixel
+  double* acc;           // [P][tiles][kNAcc]
+  double* logl;          // [P]
+  float* grad;           // [P][d]
+};
+
+constexpr int kMaxGroup = 12;
+
+// Systems that share one launch (same kernel configuration). Passed by value.
+struct Group {
+  int nsys;
+  int block0[kMaxGroup + 1];  // first block of each system; block0[nsys] = grid size
+  SysDesc sys[kMaxGroup];
+};
+
+}  // namespace glens

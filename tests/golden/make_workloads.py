@@ -19,7 +19,7 @@ import synth  # noqa: E402
 OUT = os.path.dirname(os.path.abspath(__file__))
 
 
-def oracle_model(spec: synth.Spec) -> oracle.Model:
+def oracle_model(spec: synth.Spec) -> oracle.Model:  # noqa: D401
     return oracle.Model(H=spec.H, W=spec.W, k=spec.k, pix=spec.pix, epl=spec.epl,
                         shear=spec.shear, lens_light=spec.lens_light, nmax=spec.nmax,
                         psf=spec.psf.astype(np.float64), sigma_bkg=spec.sigma_bkg,
