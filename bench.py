@@ -1,0 +1,216 @@
+"""Benchmark: batched log-likelihood + gradient evaluations per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+
+Workload (synthetic, seed-fixed): EPL + shear lens, Sersic lens light, Sersic + shapelet
+(n_max = 6) source on a 60 x 60 image at 0.065"/px, 2x supersampled, Moffat 21 x 21 PSF,
+4096 parameter vectors (2048 near the seed truth, 2048 from a broadened prior); the
+observed image is the stored seed-0 image written by the oracle. A step is one
+gl_loglik_grad call over the 4096 vectors (decode, sub-pixel forward, PSF + likelihood,
+adjoint), with inputs resident in HBM.
+
+Prints one JSON line: the metric, the roofline of the dominant kernel (algorithmic FLOPs of
+the op-count model below over its HIP-event duration), and the FP64 oracle timed on the
+host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+SERIES_TOL_FP32 = 6e-8     # series length counted by the op model (FP32 resolution)
+
+# ------------------------------------------------------------------------------------------
+# Algorithmic op-count model (frozen; FMA = 2, add / mul / compare = 1, each transcendental
+# (exp, log, sqrt, reciprocal, atan) = 1). Counts follow the formulas of the model as written
+# out in the forward and adjoint equations, per unit of work:
+#   sub-pixel forward:  mass 52 + 7 N(eps) [N = series terms at FP32 resolution],
+#                       Sersic 16 (+2 lens offsets), shapelets 2 + 2(1 + 4(n-1)) + 3M + 6,
+#                       sum + downsample 3
+#   pixel:              PSF 2 K^2, likelihood 11, adjoint seed 7, adjoint PSF 2 K^2, scale 1
+#   sub-pixel adjoint:  mass 52 + 21 N + 142, source Sersic 52, lens Sersic 58,
+#                       shapelets 49 + 11 M + 16 (n = n_max, M coefficients), centre 6, 2
+# ------------------------------------------------------------------------------------------
+
+def series_terms(eps_abs: np.ndarray) -> np.ndarray:
+    e = np.clip(np.asarray(eps_abs, np.float64), 1e-30, 0.6)
+    n = np.ceil(np.log(SERIES_TOL_FP32 * (1 - e)) / np.log(e))
+    return np.clip(n, 1, None)
+
+
+def flops_model(H, W, k, K, nmax, lens_light, N_mean, sie=False):
+    M = 0 if nmax < 0 else (nmax + 1) * (nmax + 2) // 2
+    S, Px = H * W * k * k, H * W
+    mass_f = 52 + 7 * N_mean
+    shp_f = 0 if nmax < 0 else 2 + 2 * (1 + 4 * max(nmax - 1, 0)) + 3 * M + 6
+    sub_f = mass_f + 16 + (18 if lens_light else 0) + shp_f + 3
+    mass_a = 52 + 21 * N_mean + 142
+    shp_a = 0 if nmax < 0 else 49 + 11 * M + 16
+    sub_a = mass_a + 52 + (58 if lens_light else 0) + shp_a + 6 + 2
+    return {
+        "subpix_fwd": S * sub_f,
+        "conv_lik": Px * (2 * K * K + 11),
+        "conv_lik_adj": Px * (2 * K * K + 11 + 7 + 2 * K * K + 1),
+        "subpix_adj": S * sub_a,
+    }
+
+
+# ------------------------------------------------------------------------------------------
+
+def csrc_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2202_07663_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("csrc_hash") != csrc_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def workload():
+    import synth
+    spec = synth.spec_c2()
+    obs = np.load(os.path.join(ROOT, "tests", "golden", f"obs_{spec.name}_s0.npy"))
+    truth = np.load(os.path.join(ROOT, "tests", "golden", f"truth_{spec.name}_s0.npy"))
+    theta = synth.draw_particles(spec, truth, 4096, seed=0)
+    return spec, obs, theta
+
+
+def cpu_baseline(spec, obs, theta, n_sample: int):
+    """The FP64 oracle (dual-number gradient) on the first n_sample vectors of the same
+    batch, on all host cores it is given."""
+    import oracle
+    from tests.helpers import oracle_model
+    om = oracle_model(spec)
+    idx = np.linspace(0, theta.shape[0] - 1, n_sample).astype(int)
+    th = theta[idx].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.loglik_grad(om, th, obs)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "logL+grad evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"{n_sample} of the 4096 vectors (evenly spaced), same image and model"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 512 MiB (to scale HBM counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(128 * 2 ** 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the hot path "
+              "shards particles across GPUs with no exchange, see the design notes)", flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2202_07663_amd as G
+
+    spec, obs, theta_np = workload()
+    P = theta_np.shape[0]
+    theta = torch.from_numpy(theta_np).cuda()
+    model = G.Model.from_spec(spec, obs)
+    ll = torch.empty(P, dtype=torch.float64, device="cuda")
+    gr = torch.empty((P, model.d), dtype=torch.float32, device="cuda")
+
+    for _ in range(args.warmup):
+        model.loglik_grad(theta, out=(ll, gr))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        model.loglik_grad(theta, out=(ll, gr))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = P / (wall / args.steps)
+    assert torch.isfinite(ll).all(), "non-finite log-likelihood in the benchmark batch"
+
+    # stage durations with HIP events on the stream the kernels run on
+    stages = None
+    for _ in range(args.stage_reps):
+        st = model.stage_times(theta, with_grad=True)
+        stages = st if stages is None else {k: stages[k] + st[k] for k in st}
+    stages = {k: v / args.stage_reps for k, v in stages.items()}
+    fwd = model.stage_times(theta, with_grad=False)
+
+    eps = np.hypot(theta_np[:, 2], theta_np[:, 3])
+    N_mean = float(series_terms(eps).mean())
+    fl = flops_model(spec.H, spec.W, spec.k, spec.psf.shape[0], spec.nmax, spec.lens_light, N_mean)
+    per_launch = {"subpix_adj": fl["subpix_adj"] * P, "subpix_fwd": fl["subpix_fwd"] * P,
+                  "conv_lik": fl["conv_lik_adj"] * P}
+    dominant = max(("subpix_adj", "subpix_fwd", "conv_lik"), key=lambda k: stages[k])
+    achieved = per_launch[dominant] / (stages[dominant] * 1e-3) / 1e12
+    total_flops = sum(per_launch.values())
+    traffic = load_traffic(dominant, "epl60_P4096")
+
+    out = {
+        "metric": "logL+grad evals/s (60x60 EPL+shapelets)",
+        "value": round(value, 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "epl60_shapelet6_k2_moffat21", "P": P, "d": model.d,
+                   "image": [spec.H, spec.W], "k_super": spec.k, "psf": spec.psf.shape[0],
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "kernel": dominant,
+                     "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "algorithmic_flop_per_launch": per_launch[dominant],
+                     "kernel_ms": round(stages[dominant], 4)},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "whole_path_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 2),
+        "loglik_only_ms": round(sum(fwd.values()), 4),
+        "flop_per_eval": round(total_flops / P),
+        "series_terms_counted": round(N_mean, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

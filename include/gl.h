@@ -113,6 +113,15 @@ int gl_loglik(gl_model* model, const float* theta, int P, double* logl, void* st
 int gl_loglik_grad(gl_model* model, const float* theta, int P, double* logl, float* grad,
                    void* stream);
 
+/* Diagnostic: run the gl_loglik_grad pipeline (with_grad = 1) or the gl_loglik pipeline
+ * (with_grad = 0) once on `stream` with HIP events between its kernels, wait for it, and
+ * write the duration of each stage in milliseconds to ms[GL_NSTAGES] (stages not run read
+ * 0): prologue, sub-pixel forward, PSF + likelihood (+ adjoint seed), sub-pixel adjoint,
+ * gradient finalize. logl and grad as in gl_loglik_grad (grad unused when with_grad = 0). */
+#define GL_NSTAGES 5
+int gl_model_stage_times(gl_model* model, const float* theta, int P, int with_grad,
+                         double* logl, float* grad, float* ms, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Priors, bijectors and the fixed-budget multi-start fit (Sec. 2.2 bijectors and
  * Jacobian-corrected posterior; Sec. 2.3 multi-start gradient descent with Adam).

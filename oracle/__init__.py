@@ -42,6 +42,7 @@ def lib():
             _build.build()
         _lib = ctypes.CDLL(_LIB_PATH)
         _lib.or_nparams.restype = ctypes.c_int
+        _lib.or_num_threads.restype = ctypes.c_int
         _lib.or_loglik_grad.restype = ctypes.c_int
         _lib.or_log_likelihood_image.restype = ctypes.c_double
     return _lib
@@ -83,6 +84,11 @@ class Model:
     @property
     def nparams(self) -> int:
         return lib().or_nparams(ctypes.byref(self.desc()))
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return lib().or_num_threads()
 
 
 def simulate(m: Model, theta) -> np.ndarray:

@@ -36,6 +36,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------------------
@@ -471,6 +475,15 @@ static Model to_model(const or_model_desc* d) {
 }
 
 int or_nparams(const or_model_desc* d) { return n_params(to_model(d)); }
+
+// Threads the parallel loops below use.
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Noiseless model images, img[P][H][W].
 void or_simulate(const or_model_desc* d, const double* theta, int P, double* img) {

@@ -140,6 +140,20 @@ class Model:
                                    _stream_ptr(stream)))
         return ll, g
 
+    STAGES = ("prologue", "subpix_fwd", "conv_lik", "subpix_adj", "finalize")
+
+    def stage_times(self, theta: torch.Tensor, with_grad: bool = True, stream=None) -> dict:
+        """Run the pipeline once with HIP events between its kernels (blocking); returns the
+        milliseconds of each stage."""
+        theta = self._theta(theta)
+        P = theta.shape[0]
+        ll = torch.empty(P, dtype=torch.float64, device=theta.device)
+        g = torch.empty((P, self.d), dtype=torch.float32, device=theta.device)
+        ms = (ctypes.c_float * 5)()
+        check(lib().gl_model_stage_times(self._h, theta.data_ptr(), P, int(with_grad),
+                                         ll.data_ptr(), g.data_ptr(), ms, _stream_ptr(stream)))
+        return dict(zip(self.STAGES, list(ms)))
+
 
 class LogLik(torch.autograd.Function):
     """log L(theta) as a differentiable function of theta [P, d] (float32, CUDA).

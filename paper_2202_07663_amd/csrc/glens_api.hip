@@ -319,12 +319,16 @@ static void set_blocks(Group& g, F per_sys) {
   g.block0[g.nsys] = b;
 }
 
-int run_group(Group& g, int key, int K, int mode, hipStream_t st) {
+int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev) {
   int rc;
+  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+  GL_HIP(mark(0));
   set_blocks(g, blocks_prologue);
   if ((rc = launch_prologue(g, st))) return rc;
+  GL_HIP(mark(1));
   set_blocks(g, blocks_subpix);
   if ((rc = launch_subpix_fwd(key, g, st))) return rc;
+  GL_HIP(mark(2));
   size_t lds = 0;
   for (int i = 0; i < g.nsys; ++i) {
     g.sys[i].mode = mode;
@@ -332,11 +336,15 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st) {
   }
   set_blocks(g, blocks_conv);
   if ((rc = launch_conv(K, g, lds, st))) return rc;
+  GL_HIP(mark(3));
   if (mode != 2) return GL_OK;
   set_blocks(g, blocks_subpix);
   if ((rc = launch_subpix_adj(key, g, st))) return rc;
+  GL_HIP(mark(4));
   set_blocks(g, blocks_prologue);
-  return launch_finalize(g, st);
+  if ((rc = launch_finalize(g, st))) return rc;
+  GL_HIP(mark(5));
+  return GL_OK;
 }
 
 }  // namespace glens
@@ -388,7 +396,7 @@ int gl_model_nparams(const gl_model* m, int* d) {
 }
 
 static int run_model(gl_model* m, const float* theta, int P, int mode, float* img, double* logl,
-                     float* grad, hipStream_t st) {
+                     float* grad, hipStream_t st, hipEvent_t* ev = nullptr) {
   const ModelCfg& c = m->sys.cfg;
   const int HW = c.H * c.W;
   const int tiles = choose_tiles(P, HW);
@@ -402,7 +410,7 @@ static int run_model(gl_model* m, const float* theta, int P, int mode, float* im
   g.sys[0].img = img;
   g.sys[0].logl = logl;
   g.sys[0].grad = grad;
-  return run_group(g, subpix_key(c), c.K, mode, st);
+  return run_group(g, subpix_key(c), c.K, mode, st, ev);
 }
 
 static int common_checks(gl_model* m, const float* theta, int P) {
@@ -438,6 +446,32 @@ int gl_loglik_grad(gl_model* m, const float* theta, int P, double* logl, float* 
   if ((rc = check_device_ptr(logl, "logl"))) return rc;
   if ((rc = check_device_ptr(grad, "grad"))) return rc;
   return run_model(m, theta, P, 2, nullptr, logl, grad, (hipStream_t)stream);
+}
+
+int gl_model_stage_times(gl_model* m, const float* theta, int P, int with_grad, double* logl,
+                         float* grad, float* ms, void* stream) {
+  clear_error();
+  int rc = common_checks(m, theta, P);
+  if (rc) return rc;
+  if (!ms) return set_error(GL_E_INVALID, "ms is NULL");
+  for (int i = 0; i < GL_NSTAGES; ++i) ms[i] = 0.f;
+  if (P == 0) return GL_OK;
+  if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
+  if ((rc = check_device_ptr(logl, "logl"))) return rc;
+  if (with_grad && (rc = check_device_ptr(grad, "grad"))) return rc;
+  hipEvent_t ev[GL_NSTAGES + 1];
+  for (auto& e : ev) GL_HIP(hipEventCreate(&e));
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_model(m, theta, P, with_grad ? 2 : 1, nullptr, logl, grad, st, ev);
+  if (rc == GL_OK) {
+    const int last = with_grad ? GL_NSTAGES : 3;
+    if (hipEventSynchronize(ev[last]) != hipSuccess) rc = set_error(GL_E_DEVICE, "event sync failed");
+    for (int i = 0; rc == GL_OK && i < last; ++i)
+      if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess)
+        rc = set_error(GL_E_DEVICE, "event timing failed");
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
 }
 
 }  // extern "C"

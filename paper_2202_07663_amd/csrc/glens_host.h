@@ -78,7 +78,8 @@ inline int blocks_conv(const SysDesc& s) { return s.P; }
 
 // Run the forward (+adjoint) pipeline for a group of systems sharing key and PSF size.
 // mode: 0 image, 1 log L, 2 log L + gradient.
-int run_group(Group& g, int key, int K, int mode, hipStream_t st);
+// ev (optional): GL_NSTAGES + 1 events, recorded before the first and after every stage.
+int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev = nullptr);
 
 int check_device_ptr(const void* p, const char* name);
 
