@@ -162,17 +162,22 @@ typedef struct gl_fit_result {
  * then the best particle by log posterior at its final position. */
 int gl_fit(gl_model* model, const gl_fit_opts* opts, gl_fit_result* out, void* stream);
 
-/* Lower-level fit state, for stepping and inspection. Buffers are device, owned by the
- * state. gl_fit_state_z returns the device pointer of z[P][d]; m and v likewise. */
+/* Lower-level fit state, for stepping and inspection. The state owns device arrays
+ * z, m, v ([P][d] FP32: unconstrained parameters and Adam moments) and a step counter.
+ * gl_fit_state_create draws the P starts from the prior (m = v = 0, step 0). */
 typedef struct gl_fit_state gl_fit_state;
 int gl_fit_state_create(gl_model* model, const gl_fit_opts* opts, gl_fit_state** out,
                         void* stream);
 int gl_fit_state_destroy(gl_fit_state* st);
-/* Run `n` Adam steps (continuing the schedule). */
+/* Run `n` Adam steps (continuing the schedule from the current step). */
 int gl_fit_state_step(gl_fit_state* st, int n, void* stream);
-/* Device pointers to the state arrays ([P][d] FP32) and the step counter. */
-int gl_fit_state_arrays(gl_fit_state* st, float** z, float** m, float** v, int* step);
-/* Evaluate log L at the current z, pick the best particle, fill *out (blocking). */
+/* Copy caller device arrays ([P][d] FP32) into the state and set the step counter. */
+int gl_fit_state_load(gl_fit_state* st, const float* z, const float* m, const float* v,
+                      int step, void* stream);
+/* Copy the state out to caller device arrays (any of them may be NULL). */
+int gl_fit_state_store(gl_fit_state* st, float* z, float* m, float* v, int* step, void* stream);
+/* Evaluate log L at the current z, pick the best particle by log L + log p~, fill *out
+ * (blocking). */
 int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
 
 /* ---------------------------------------------------------------------------------------

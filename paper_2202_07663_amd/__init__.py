@@ -19,7 +19,8 @@ import torch
 from . import _lib
 from ._lib import GlError, check, lib
 
-__all__ = ["Model", "LogLik", "GlError", "param_names", "nparams"]
+__all__ = ["Model", "LogLik", "FitState", "fit", "Server", "GlError", "param_names", "nparams",
+           "make_priors", "make_fit_opts", "result_dict"]
 
 
 def nparams(mass: str, shear: bool, lens_light: bool, shapelet_nmax: int) -> int:
@@ -172,3 +173,146 @@ class LogLik(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return (grad_out.to(g.dtype)[:, None] * g), None
+
+
+# ------------------------------------------------------------------------------------------
+# Multi-start fit
+# ------------------------------------------------------------------------------------------
+
+def make_priors(priors) -> "ctypes.Array":
+    """gl_prior array from a list of dicts {family, mu, sigma, lo, hi}."""
+    arr = (_lib.Prior * len(priors))()
+    for i, p in enumerate(priors):
+        arr[i] = _lib.Prior(int(p["family"]), float(p.get("mu", 0.0)), float(p.get("sigma", 1.0)),
+                            float(p.get("lo", 0.0)), float(p.get("hi", 0.0)))
+    return arr
+
+
+def make_fit_opts(P, K, priors, lr0=1e-2, lr1=1e-3, seed=0, beta1=0.9, beta2=0.999, eps=1e-8):
+    pa = make_priors(priors)
+    o = _lib.FitOpts(P, K, lr0, lr1, beta1, beta2, eps, seed,
+                     ctypes.cast(pa, ctypes.POINTER(_lib.Prior)))
+    return o, pa
+
+
+def result_dict(r) -> dict:
+    return {"status": r.status, "d": r.d, "best": r.best,
+            "theta_best": np.array(r.theta_best[:r.d], np.float32), "logl_best": r.logl_best,
+            "logpost_best": r.logpost_best, "chi2nu": r.chi2nu, "t_submit": r.t_submit,
+            "t_admit": r.t_admit, "t_done": r.t_done}
+
+
+class FitState:
+    """Device state of one multi-start fit (z, Adam moments, step) on a Model.
+    Starts are drawn from the prior on creation."""
+
+    def __init__(self, model: Model, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0,
+                 stream=None):
+        assert len(priors) == model.d
+        self.model, self.P, self.K = model, P, K
+        opts, self._pa = make_fit_opts(P, K, priors, lr0, lr1, seed)
+        h = ctypes.c_void_p()
+        check(lib().gl_fit_state_create(model._h, ctypes.byref(opts), ctypes.byref(h),
+                                        _stream_ptr(stream)))
+        self._h = h
+
+    def step(self, n: int = 1, stream=None):
+        check(lib().gl_fit_state_step(self._h, n, _stream_ptr(stream)))
+
+    def load(self, z: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, stream=None):
+        z, m, v = (t.contiguous() for t in (z, m, v))
+        for t in (z, m, v):
+            assert t.is_cuda and t.dtype == torch.float32 and t.shape == (self.P, self.model.d)
+        check(lib().gl_fit_state_load(self._h, z.data_ptr(), m.data_ptr(), v.data_ptr(), step,
+                                      _stream_ptr(stream)))
+        self._keep = (z, m, v)
+
+    def store(self, stream=None):
+        shape = (self.P, self.model.d)
+        z, m, v = (torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(3))
+        step = ctypes.c_int()
+        check(lib().gl_fit_state_store(self._h, z.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                       ctypes.byref(step), _stream_ptr(stream)))
+        return z, m, v, step.value
+
+    def result(self, stream=None) -> dict:
+        r = _lib.FitResult()
+        check(lib().gl_fit_state_result(self._h, ctypes.byref(r), _stream_ptr(stream)))
+        return result_dict(r)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_fit_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit(model: Model, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0, stream=None) -> dict:
+    """One fixed-budget multi-start fit of one system (blocking); returns the best particle."""
+    opts, _keep = make_fit_opts(P, K, priors, lr0, lr1, seed)
+    r = _lib.FitResult()
+    check(lib().gl_fit(model._h, ctypes.byref(opts), ctypes.byref(r), _stream_ptr(stream)))
+    return result_dict(r)
+
+
+# ------------------------------------------------------------------------------------------
+# Continuous-batching server
+# ------------------------------------------------------------------------------------------
+
+class Server:
+    """Fit server on the current GPU: gl_submit queues a system, gl_poll collects results."""
+
+    def __init__(self, hbm_budget_bytes: int = 16 << 30, max_systems: int = 16,
+                 steps_per_tick: int = 10):
+        o = _lib.ServerOpts(hbm_budget_bytes, max_systems, steps_per_tick)
+        h = ctypes.c_void_p()
+        check(lib().gl_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, spec, obs, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0) -> int:
+        """Queue one fit of the system `spec` (a synth.Spec-like object) with image `obs`."""
+        desc, _keep = make_desc(spec.H, spec.W, spec.pix, spec.k, "epl" if spec.epl else "sie",
+                                spec.shear, spec.lens_light, spec.nmax, spec.psf, obs,
+                                spec.sigma_bkg, spec.t_exp, spec.gain)
+        opts, _pa = make_fit_opts(P, K, priors, lr0, lr1, seed)
+        t = ctypes.c_uint64()
+        check(lib().gl_submit(self._h, ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the result dict (the ticket is then released)."""
+        r = _lib.FitResult()
+        rc = check(lib().gl_poll(self._h, ticket, ctypes.byref(r)))
+        return None if rc == _lib.GL_PENDING else result_dict(r)
+
+    def wait(self, ticket: int, timeout: float = 600.0, interval: float = 0.002) -> dict:
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(interval)
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        check(lib().gl_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

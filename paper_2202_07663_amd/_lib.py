@@ -78,8 +78,8 @@ _SIGNATURES = {
     "gl_fit_state_create": [_vp, ctypes.POINTER(FitOpts), ctypes.POINTER(_vp), _vp],
     "gl_fit_state_destroy": [_vp],
     "gl_fit_state_step": [_vp, _i, _vp],
-    "gl_fit_state_arrays": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
-                            ctypes.POINTER(_i)],
+    "gl_fit_state_load": [_vp, _vp, _vp, _vp, _i, _vp],
+    "gl_fit_state_store": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i), _vp],
     "gl_fit_state_result": [_vp, ctypes.POINTER(FitResult), _vp],
     "gl_server_create": [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)],
     "gl_server_destroy": [_vp],

@@ -39,6 +39,13 @@ namespace glens {
 
 constexpr float kInvSqrtPi = 0.56418958354775628f;
 
+// System of a Group that owns block b of a grouped launch.
+__device__ __forceinline__ int find_sys(const Group& g, int b) {
+  int i = 0;
+  while (i + 1 < g.nsys && b >= g.block0[i + 1]) ++i;
+  return i;
+}
+
 // ------------------------------------------------------------------------------------------
 // Per-particle decode (prologue). Double precision: it runs once per particle.
 // ------------------------------------------------------------------------------------------

@@ -23,12 +23,6 @@ constexpr int kSubThreads = 256;
 constexpr int kConvThreads = 256;
 constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
 
-__device__ __forceinline__ int find_sys(const Group& g, int b) {
-  int i = 0;
-  while (i + 1 < g.nsys && b >= g.block0[i + 1]) ++i;
-  return i;
-}
-
 // --- bijectors (Sec. 2.2): exp for log-normal priors, sigmoid onto (lo, hi) for truncated
 // normal and uniform priors, identity for normal priors ---
 __device__ __forceinline__ float bijector_fwd(const Prior& pr, float z) {
@@ -161,7 +155,7 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
     if (mode == 2) Bm[idx] = 0.f;
   }
   __syncthreads();
-  double ll = 0.0;
+  double ll = 0.0, c2 = 0.0;
   const float* obs = s.obs;
   for (int sidx = threadIdx.x; sidx < nstrip * W; sidx += blockDim.x) {
     const int st = sidx / W, j = sidx - st * W, i0 = st * R;
@@ -179,7 +173,9 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
         const float s2 = s.s2b + pos * s.inv_gt;
         const float res = obs[i * W + j] - m;
         const float is2 = 1.0f / s2;
-        ll += double(res * res * is2 + logf(6.283185307179586f * s2));
+        const float chi = res * res * is2;
+        c2 += double(chi);
+        ll += double(chi + logf(6.283185307179586f * s2));
         if (mode == 2) {
           const float sp = m > 0.f ? s.inv_gt : 0.f;
           Bm[(i + C) * Wp + j + C] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
@@ -192,6 +188,10 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
   if (threadIdx.x == 0) {
     const double v = -0.5 * tot;
     s.logl[part] = isfinite(v) ? v : -INFINITY;
+  }
+  if (s.chi2) {
+    const double ctot = block_sum(c2, red);
+    if (threadIdx.x == 0) s.chi2[part] = ctot;
   }
   if (mode != 2) return;
   __syncthreads();

@@ -96,9 +96,16 @@ struct SysDesc {
   const float* psf;      // K*K
   const float* psf_flip; // K*K, flipped in both axes
   const float* theta;    // [P][d] physical parameters, or null if z is given
-  const float* z;        // [P][d] unconstrained parameters (fit), or null
+  float* z;              // [P][d] unconstrained parameters (fit), or null
   const Prior* prior;    // [d] (fit)
   float* theta_out;      // [P][d] physical parameters written when z is given
+  float* mom1;           // [P][d] Adam first moment (fit)
+  float* mom2;           // [P][d] Adam second moment (fit)
+  double* logpost;       // [P] log L + log p~ (fit result)
+  double* chi2;          // [P] chi^2 (optional output of the likelihood pass)
+  int step, nsteps;      // 0-based Adam step, schedule length K
+  float lr0, lr1, beta1, beta2, eps_adam;
+  uint32_t seed_lo, seed_hi;
   PConst* pc;            // [P]
   float* m0;             // [P][H][W] downsampled image before the PSF
   float* img;            // [P][H][W] model image (mode 0)
@@ -108,7 +115,7 @@ struct SysDesc {
   float* grad;           // [P][d]
 };
 
-constexpr int kMaxGroup = 12;
+constexpr int kMaxGroup = 10;
 
 // Systems that share one launch (same kernel configuration). Passed by value.
 struct Group {
@@ -116,5 +123,6 @@ struct Group {
   int block0[kMaxGroup + 1];  // first block of each system; block0[nsys] = grid size
   SysDesc sys[kMaxGroup];
 };
+static_assert(sizeof(Group) <= 4000, "kernel argument size");
 
 }  // namespace glens

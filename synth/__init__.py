@@ -227,3 +227,41 @@ def add_noise(clean: np.ndarray, seed: int, sigma_bkg: float, t_exp: float,
     lam = np.maximum(np.asarray(clean, np.float64), 0.0) * gain * t_exp
     shot = rng.poisson(lam) / (gain * t_exp)
     return (shot + rng.normal(0.0, sigma_bkg, size=np.shape(clean))).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------------------
+# Fit priors (passed to the fit as gl_prior entries). Families and widths follow the
+# paper's broadened prior (blue entries of eq. sim-dist) where its parameter and scale
+# match these workloads; lens-light radius, source radius and source intensity are centred
+# on these workloads' draws instead. Shapelets (no prior in the paper): beta uniform on
+# (0.02, 0.4), coefficients N(0, 10).
+# ----------------------------------------------------------------------------------------
+NORMAL, LOGNORMAL, TRUNCNORMAL, UNIFORM = 0, 1, 2, 3
+
+
+def fit_priors(spec: Spec) -> list:
+    def N(mu, s):
+        return {"family": NORMAL, "mu": mu, "sigma": s, "lo": 0.0, "hi": 0.0}
+
+    def LN(m, s):
+        return {"family": LOGNORMAL, "mu": float(np.log(m)), "sigma": s, "lo": 0.0, "hi": 0.0}
+
+    def TN(mu, s, lo, hi):
+        return {"family": TRUNCNORMAL, "mu": mu, "sigma": s, "lo": lo, "hi": hi}
+
+    def U(lo, hi):
+        return {"family": UNIFORM, "mu": 0.0, "sigma": 1.0, "lo": lo, "hi": hi}
+
+    pr = [LN(1.25, 0.4)] + ([TN(2.0, 0.5, 1.0, 3.0)] if spec.epl else [])
+    pr += [N(0, 0.2), N(0, 0.2), N(0, 0.1), N(0, 0.1)]
+    if spec.shear:
+        pr += [N(0, 0.1), N(0, 0.1)]
+    if spec.lens_light:
+        pr += [LN(1.0, 0.5), U(0.5, 8.0), TN(0, 0.1, -0.15, 0.15), TN(0, 0.1, -0.15, 0.15),
+               N(0, 0.02), N(0, 0.02), LN(300.0, 0.5)]
+    pr += [LN(0.25, 0.5), U(0.5, 8.0), TN(0, 0.3, -0.5, 0.5), TN(0, 0.3, -0.5, 0.5),
+           N(0, 0.5), N(0, 0.5), LN(12.0, 0.9)]
+    if spec.nmax >= 0:
+        pr += [U(0.02, 0.4)] + [N(0, 10.0)] * n_shapelet_coeffs(spec.nmax)
+    assert len(pr) == spec.d
+    return [dict(p) for p in pr]
