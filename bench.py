@@ -114,6 +114,102 @@ def cpu_baseline(spec, obs, theta, n_sample: int):
             "sample": f"{n_sample} of the 4096 vectors (evenly spaced), same image and model"}
 
 
+# ------------------------------------------------------------------------------------------
+# Serving: a stream of systems of mixed image size and component set (sizes {40, 60, 80,
+# 100} px at k = 2 with a Moffat 21 x 21 PSF; SIE or EPL; lens light on or off; shapelets
+# none / n_max 4, 6, 8; P a multiple of 256 in [512, 4096]; fixed Adam budget K). The
+# observed images come from gl_simulate of a seeded truth plus seeded noise.
+# ------------------------------------------------------------------------------------------
+
+def make_stream(n, seed, G):
+    import synth
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        N = int(rng.choice([40, 60, 80, 100]))
+        epl = bool(rng.integers(2))
+        ll = bool(rng.integers(2))
+        nmax = int(rng.choice([-1, 4, 6, 8]))
+        P = int(256 * rng.integers(2, 17))
+        spec = synth.spec_custom(N, 2, epl, ll, nmax, K=21)
+        truth = synth.draw_truth(spec, 1000 + i)
+        import torch
+        m = G.Model.from_spec(spec, None)
+        clean = m.simulate(torch.from_numpy(truth[None, :]).cuda()).cpu().numpy()[0]
+        m.close()
+        obs = synth.add_noise(clean, 1000 + i, spec.sigma_bkg, spec.t_exp)
+        out.append((spec, obs, P, synth.fit_priors(spec)))
+    return out
+
+
+def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16):
+    import threading
+    import paper_2202_07663_amd as G
+    stream = make_stream(n_systems, seed, G)
+    # 1. the plain loop: one system at a time, each fit run to completion
+    service = []
+    for spec, obs, P, pri in stream:
+        t0 = time.perf_counter()
+        m = G.Model.from_spec(spec, obs)
+        r = G.fit(m, P, K, pri, seed=7)
+        m.close()
+        service.append(time.perf_counter() - t0)
+        assert r["status"] == 0
+    mu_serial = len(service) / sum(service)
+
+    def serve(arrivals):
+        srv = G.Server(hbm_budget_bytes=64 << 30, max_systems=max_systems,
+                       steps_per_tick=steps_per_tick)
+        tickets = [None] * len(stream)
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i, (spec, obs, P, pri) in enumerate(stream):
+                wait = arrivals[i] - (time.perf_counter() - t_start)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets[i] = srv.submit(spec, obs, P, K, pri, seed=7)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        makespan = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        assert all(r["status"] == 0 for r in res)
+        lat = np.array([(r["t_done"] - r["t_submit"]) * 1e-9 for r in res])
+        return makespan, lat, st
+
+    # 2. burst: every request at t = 0 (throughput)
+    makespan, lat_burst, st_burst = serve(np.zeros(len(stream)))
+    # 3. Poisson arrivals at 0.8 x the serial loop's rate (latency at stable load)
+    lam = 0.8 * mu_serial
+    arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / lam, len(stream)))
+    _, lat, _ = serve(arr)
+    # the serial loop under the same arrivals: a FIFO single server with the measured
+    # service times
+    fin, lat_serial = 0.0, []
+    for a, sv in zip(arr, service):
+        fin = max(fin, a) + sv
+        lat_serial.append(fin - a)
+    lat_serial = np.array(lat_serial)
+    q = lambda x, p: float(np.percentile(x, p))  # noqa: E731
+    return {
+        "systems": len(stream), "K": K, "steps_per_tick": steps_per_tick,
+        "max_systems": max_systems,
+        "fits_per_hour_served": round(3600 * len(stream) / makespan, 1),
+        "fits_per_hour_serial": round(3600 * mu_serial, 1),
+        "throughput_gain": round(sum(service) / makespan, 3),
+        "poisson_rate_per_s": round(lam, 4),
+        "p50_latency_s": round(q(lat, 50), 4), "p99_latency_s": round(q(lat, 99), 4),
+        "p50_latency_serial_s": round(q(lat_serial, 50), 4),
+        "p99_latency_serial_s": round(q(lat_serial, 99), 4),
+        "burst_p50_s": round(q(lat_burst, 50), 4), "burst_p99_s": round(q(lat_burst, 99), 4),
+        "hbm_peak_bytes": int(st_burst["hbm_peak"]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +218,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--serve-systems", type=int, default=32,
+                    help="systems in the serving stream (0 skips the serving measurement)")
+    ap.add_argument("--serve-steps", type=int, default=300, help="Adam steps per fit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 512 MiB (to scale HBM counters) and exit")
     args = ap.parse_args()
@@ -180,7 +279,7 @@ def main():
     traffic = load_traffic(dominant, "epl60_P4096")
 
     out = {
-        "metric": "logL+grad evals/s (60x60 EPL+shapelets)",
+        "metric": "logL+grad evals/s (60x60 EPL+shapelets); fits/hour + p50/p99 latency",
         "value": round(value, 1),
         "unit": "evals/s",
         "n_gpus": 1,
@@ -207,6 +306,8 @@ def main():
         "flop_per_eval": round(total_flops / P),
         "series_terms_counted": round(N_mean, 2),
     }
+    if args.serve_systems > 0:
+        out["serving"] = serving_bench(args.serve_systems, args.serve_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -190,6 +190,10 @@ typedef struct gl_server_opts {
   size_t hbm_budget_bytes; /* device memory the active systems may hold (state + scratch) */
   int max_systems;         /* active-system slots */
   int steps_per_tick;      /* Adam steps per system per tick, >= 1 */
+  double fill_subpixels;   /* admit while the active systems' sub-pixel evaluations per
+                              step (sum of P H W k^2) stay below this; one system is always
+                              admitted when none is active. 0 selects 6e7, about what fills
+                              one GPU; a huge value admits by slots and budget only */
 } gl_server_opts;
 
 typedef struct gl_server gl_server;

@@ -268,8 +268,8 @@ class Server:
     """Fit server on the current GPU: gl_submit queues a system, gl_poll collects results."""
 
     def __init__(self, hbm_budget_bytes: int = 16 << 30, max_systems: int = 16,
-                 steps_per_tick: int = 10):
-        o = _lib.ServerOpts(hbm_budget_bytes, max_systems, steps_per_tick)
+                 steps_per_tick: int = 10, fill_subpixels: float = 0.0):
+        o = _lib.ServerOpts(hbm_budget_bytes, max_systems, steps_per_tick, fill_subpixels)
         h = ctypes.c_void_p()
         check(lib().gl_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -54,7 +54,7 @@ class FitResult(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_systems", ctypes.c_int),
-                ("steps_per_tick", ctypes.c_int)]
+                ("steps_per_tick", ctypes.c_int), ("fill_subpixels", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):

@@ -129,12 +129,16 @@ GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light,
   c.mj12 = float(j12);
   c.mj22 = float(j22);
   // series: terms until the tail bound |eps|^N / (1 - |eps|) drops below the tolerance
-  int nt = 1;
+  // (FP64 value series), and below the looser derivative tolerance (adjoint series)
+  int nt = 1, ntd = 1;
   if (eabs > 1e-30) {
     nt = int(ceil(log(kSeriesTol * (1.0 - eabs)) / log(eabs)));
     nt = nt < 1 ? 1 : (nt > kMaxTerms ? kMaxTerms : nt);
+    ntd = int(ceil(log(kSeriesTolDeriv * (1.0 - eabs)) / log(eabs))) + 1;
+    ntd = ntd < 1 ? 1 : (ntd > nt ? nt : ntd);
   }
   c.nterms = nt;
+  c.nterms_d = ntd;
   double cn = 1.0, dsum = 0.0;
   for (int n = 0; n < kMaxTerms; ++n) {
     if (n > 0) {
@@ -143,8 +147,10 @@ GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light,
       dsum += 1.0 / a + 1.0 / b;
     }
     c.c[n] = n < nt ? cn : 0.0;
-    c.dc[n] = n < nt ? float(cn * dsum) : 0.f;
+    c.dc[n] = n < ntd ? float(cn * dsum) : 0.f;
+    if (n > 0) c.nc[n - 1] = n < ntd ? float(n * cn) : 0.f;
   }
+  c.nc[kMaxTerms - 1] = 0.f;
   // SIE closed form: s = sqrt(conj(eps)), S_1(X) = atan(s u) / (s u), u = w / |w|
   c.sie_closed = (mass == 0 && eabs >= kSieClosedMin) ? 1 : 0;
   if (c.sie_closed) {
@@ -175,6 +181,66 @@ GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light,
 }
 
 // ------------------------------------------------------------------------------------------
+// Double-precision helpers for the ray trace, for the argument ranges met there (normal,
+// finite, positive arguments). Written from the mathematics:
+//   rcp: hardware estimate refined by two Newton steps r <- r (2 - x r);
+//   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m-1)/(m+1),
+//        |s| <= 0.172, summed to s^15 (relative error < 1e-15);
+//   exp: x = k ln2 + r with |r| <= ln2/2 (Cody-Waite reduction, ln2 as a double plus its
+//        tail), e^r by its Taylor series to r^12 (truncation < 2e-16), then scaled by 2^k.
+// ------------------------------------------------------------------------------------------
+constexpr double kLn2 = 0.6931471805599453;        // nearest double to ln 2
+constexpr double kLn2Tail = 2.3190468138462996e-17;  // ln 2 - kLn2
+constexpr double kInvLn2 = 1.4426950408889634;
+
+__device__ __forceinline__ double rcp_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__host__ inline double rcp_f64(double x) { return 1.0 / x; }
+
+GL_HD double log_f64(double x) {
+  int e;
+  double m = frexp(x, &e);  // [0.5, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) * rcp_f64(m + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 15.0;
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  const double de = double(e);
+  return fma(de, kLn2, fma(de, kLn2Tail, 2.0 * s * p));
+}
+
+GL_HD double exp_f64(double x) {
+  const double k = rint(x * kInvLn2);
+  const double r = fma(-k, kLn2Tail, fma(-k, kLn2, x));
+  double p = 1.0 / 479001600.0;  // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, int(k));
+}
+
+// ------------------------------------------------------------------------------------------
 // Sub-pixel math
 // ------------------------------------------------------------------------------------------
 
@@ -201,19 +267,22 @@ struct MassState {
 };
 
 // EPL / SIE deflection plus shear at image position (x, y); beta = x - alpha - alpha_ext.
-// ADJ: also dS/dX and dS/dt (FP32).
+// ADJ: also dS/dX and dS/dt (FP32). cs / ncs / dcs: the particle's coefficient tables
+// c.c / c.nc / c.dc (the kernels pass copies staged in LDS).
 template <int MASS, bool ADJ>
-GL_HD void mass_eval(const PConst& c, double x, double y, MassState& m) {
+GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
+                     const float* __restrict__ ncs, const float* __restrict__ dcs, double x,
+                     double y, MassState& m) {
   const double zr = x - c.xc, zi = y - c.yc;
   const double e1 = c.e1, e2 = c.e2;
   const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
   double w2 = wr * wr + wi * wi;
   m.floored = w2 < c.w2floor;
   w2 = m.floored ? c.w2floor : w2;
-  const double inv_w2 = 1.0 / w2;
+  const double inv_w2 = rcp_f64(w2);
   const double u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0 * wr * wi * inv_w2;
   const double Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
-  const double lnw2 = log(w2);
+  const double lnw2 = log_f64(w2);
   double Sr, Si, A;
   if (MASS == 0 && c.sie_closed) {
     // S_1(X) = atan(zeta) / zeta, zeta = s w / |w|; atan of |zeta| < 1 in closed form
@@ -237,35 +306,48 @@ GL_HD void mass_eval(const PConst& c, double x, double y, MassState& m) {
     }
   } else {
     const double yr = -Xr, yi = -Xi;
-    const float yrf = float(yr), yif = float(yi);
+    // Horner from the top, four terms per trip; coefficients past the series lengths are
+    // zero, so rounding the lengths up to a multiple of four is exact. The value series
+    // S(y) = sum c_n y^n runs in FP64 over all terms; the adjoint's derivative series
+    // S'(y) = sum (n+1) c_{n+1} y^n and dS/dt = sum dc_n y^n run in FP32 over the first
+    // nterms_d terms only.
     double sr = 0.0, si = 0.0;
-    float dr = 0.f, di = 0.f, tr = 0.f, ti = 0.f;
-    const int nt = c.nterms;
-    for (int n = nt - 1; n >= 0; --n) {
-      if (ADJ) {
-        const float ndr = dr * yrf - di * yif + float(sr);
-        const float ndi = dr * yif + di * yrf + float(si);
-        dr = ndr;
-        di = ndi;
-        if (MASS == 1) {
-          const float ntr = tr * yrf - ti * yif + c.dc[n];
-          const float nti = tr * yif + ti * yrf;
-          tr = ntr;
-          ti = nti;
+    const int nt4 = (c.nterms + 3) & ~3;
+    const int nd4 = ADJ ? ((c.nterms_d + 3) & ~3) : 0;
+    for (int n0 = nt4 - 4; n0 >= nd4; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const double nsr = fma(sr, yr, fma(-si, yi, cs[n0 + q]));
+        si = fma(sr, yi, si * yr);
+        sr = nsr;
+      }
+    }
+    if (ADJ) {
+      const float yrf = float(yr), yif = float(yi);
+      float dr = 0.f, di = 0.f, tr = 0.f, ti = 0.f;
+      for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+        for (int q = 3; q >= 0; --q) {
+          const int n = n0 + q;
+          const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
+          si = fma(sr, yi, si * yr);
+          sr = nsr;
+          const float ndr = fmaf(dr, yrf, fmaf(-di, yif, ncs[n]));
+          di = fmaf(dr, yif, di * yrf);
+          dr = ndr;
+          if (MASS == 1) {
+            const float ntr = fmaf(tr, yrf, fmaf(-ti, yif, dcs[n]));
+            ti = fmaf(tr, yif, ti * yrf);
+            tr = ntr;
+          }
         }
       }
-      const double nsr = sr * yr - si * yi + c.c[n];
-      const double nsi = sr * yi + si * yr;
-      sr = nsr;
-      si = nsi;
-    }
-    Sr = sr;
-    Si = si;
-    if (ADJ) {
       m.SX = {-dr, -di};  // d/dX = -d/dy
       m.St = {tr, ti};
     }
-    A = exp(c.tlnb - 0.5 * c.t * lnw2);
+    Sr = sr;
+    Si = si;
+    A = exp_f64(c.tlnb - 0.5 * c.t * lnw2);
   }
   const double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
   // beta - x_s = x - alpha - alpha_ext - x_s
@@ -373,8 +455,14 @@ GL_HD void hermite(float u, float* h) {
     h[n + 1] = sqrtf(2.0f / (n + 1)) * u * h[n] - sqrtf(float(n) / (n + 1)) * h[n - 1];
 }
 
-// Shapelet intensity at offset (sdx, sdy) from the source centre: G(u, v) sum_k c'_k h_n1(u) h_n2(v), c'_k = c_k / (beta sqrt(pi)),
-// ordered n = 0..NMAX, n1 = n..0, n2 = n - n1.
+// Index of coefficient (n1, n2) in the order n = 0..NMAX, n1 = n..0, n2 = n - n1.
+__host__ __device__ constexpr int shp_index(int n1, int n2) {
+  return (n1 + n2) * (n1 + n2 + 1) / 2 + n2;
+}
+
+// Shapelet intensity at offset (sdx, sdy) from the source centre:
+// G(u, v) sum_k c'_k h_n1(u) h_n2(v), c'_k = c_k / (beta sqrt(pi)), G = exp(-(u^2+v^2)/2),
+// summed as U = sum_n1 h_n1(u) T_n1 with T_n1 = sum_n2 c'_(n1,n2) h_n2(v).
 template <int NMAX>
 GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
   const float u = sdx * c.inv_beta, v = sdy * c.inv_beta;
@@ -382,15 +470,22 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
   hermite<NMAX>(u, hu);
   hermite<NMAX>(v, hv);
   float U = 0.f;
-  int k = 0;
 #pragma unroll
-  for (int n = 0; n <= NMAX; ++n)
+  for (int n1 = 0; n1 <= NMAX; ++n1) {
+    float T = 0.f;
 #pragma unroll
-    for (int n1 = n; n1 >= 0; --n1, ++k) U += c.shp[k] * hu[n1] * hv[n - n1];
+    for (int n2 = 0; n2 <= NMAX - n1; ++n2) T = fmaf(c.shp[shp_index(n1, n2)], hv[n2], T);
+    U = fmaf(hu[n1], T, U);
+  }
   return expf(-0.5f * (u * u + v * v)) * U;
 }
 
-// Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y).
+// Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y), using
+// h_n' = sqrt(2n) h_{n-1} for the normalised Hermite polynomials:
+//   dI/du = G (sum_n1 sqrt(2 n1) h_{n1-1}(u) T_n1 - u U),
+//   dI/dv = G (sum_n1 h_n1(u) Tv_n1 - v U),  Tv_n1 = sum_n2 c' sqrt(2 n2) h_{n2-1}(v),
+//   dI/dc_k = G h_n1(u) h_n2(v) / (beta sqrt(pi)) (the 1/(beta sqrt(pi)) is applied when
+//   the accumulators are mapped onto the gradient).
 template <int NMAX>
 GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float* acc, float& gbx,
                          float& gby) {
@@ -402,20 +497,27 @@ GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float*
   const float G = expf(-0.5f * (u * u + v * v));
   const float sg = sb * G;
   float U = 0.f, Uu = 0.f, Uv = 0.f;
-  int k = 0;
 #pragma unroll
-  for (int n = 0; n <= NMAX; ++n) {
+  for (int n1 = 0; n1 <= NMAX; ++n1) {
+    float T = 0.f, Tv = 0.f;
 #pragma unroll
-    for (int n1 = n; n1 >= 0; --n1, ++k) {
-      const int n2 = n - n1;
-      const float ck = c.shp[k];
-      const float hh = hu[n1] * hv[n2];
-      U += ck * hh;
-      if (n1 > 0) Uu += ck * sqrtf(2.0f * n1) * hu[n1 - 1] * hv[n2];
-      if (n2 > 0) Uv += ck * sqrtf(2.0f * n2) * hu[n1] * hv[n2 - 1];
-      acc[A_SHP_C + k] += sg * hh;
+    for (int n2 = 0; n2 <= NMAX - n1; ++n2) {
+      const float ck = c.shp[shp_index(n1, n2)];
+      T = fmaf(ck, hv[n2], T);
+      if (n2 > 0) Tv = fmaf(ck, sqrtf(2.0f * n2) * hv[n2 - 1], Tv);
     }
+    U = fmaf(hu[n1], T, U);
+    Uv = fmaf(hu[n1], Tv, Uv);
+    if (n1 > 0) Uu = fmaf(sqrtf(2.0f * n1) * hu[n1 - 1], T, Uu);
   }
+  float hvs[NMAX + 1];
+#pragma unroll
+  for (int n2 = 0; n2 <= NMAX; ++n2) hvs[n2] = sg * hv[n2];
+#pragma unroll
+  for (int n1 = 0; n1 <= NMAX; ++n1)
+#pragma unroll
+    for (int n2 = 0; n2 <= NMAX - n1; ++n2)
+      acc[A_SHP_C + shp_index(n1, n2)] = fmaf(hu[n1], hvs[n2], acc[A_SHP_C + shp_index(n1, n2)]);
   const float I = G * U;
   const float Iu = G * (Uu - u * U), Iv = G * (Uv - v * U);
   acc[A_SHP_BETA] += sb * (-I - u * Iu - v * Iv) * ib;

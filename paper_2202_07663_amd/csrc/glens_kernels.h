@@ -57,11 +57,22 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
 // ------------------------------------------------------------------------------------------
 // sub-pixel forward: lanes own pixels, loop over the k x k sub-pixels
 // ------------------------------------------------------------------------------------------
+// Copies the particle's series coefficients to LDS (read uniformly by every lane).
+__device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float* s_nc,
+                                             float* s_dc) {
+  for (int n = threadIdx.x; n < kMaxTerms; n += blockDim.x) {
+    s_c[n] = c.c[n];
+    s_nc[n] = c.nc[n];
+    s_dc[n] = c.dc[n];
+  }
+  __syncthreads();
+}
+
 template <int MASS, int NMAX>
-__device__ __forceinline__ float surface_brightness(const PConst& c, int lens_light, double x,
-                                                    double y) {
+__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c,
+                                                    int lens_light, double x, double y) {
   MassState m;
-  mass_eval<MASS, false>(c, x, y, m);
+  mass_eval<MASS, false>(c, s_c, nullptr, nullptr, x, y, m);
   float v = sersic_fwd(c.src, m.sdx, m.sdy);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy);
   if (lens_light) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
@@ -75,6 +86,9 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int lb = blockIdx.x - g.block0[si];
   const int part = lb / s.tiles, tile = lb - part * s.tiles;
   const PConst& c = s.pc[part];
+  __shared__ double s_c[kMaxTerms];
+  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
+  stage_series(c, s_c, s_nc, s_dc);
   const int HW = s.H * s.W, W = s.W, k = s.k;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
@@ -86,7 +100,7 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
       const double y = s.y0 + double(i * k + a) * s.dxs;
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
-        sum += surface_brightness<MASS, NMAX>(c, s.lens_light, x, y);
+        sum += surface_brightness<MASS, NMAX>(c, s_c, s.lens_light, x, y);
       }
     }
     out[pix] = sum * s.inv_k2;
@@ -226,6 +240,9 @@ __global__ void __launch_bounds__(kSubThreads) subpix_adj_kernel(Group g) {
   const int lb = blockIdx.x - g.block0[si];
   const int part = lb / s.tiles, tile = lb - part * s.tiles;
   const PConst& c = s.pc[part];
+  __shared__ double s_c[kMaxTerms];
+  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
+  stage_series(c, s_c, s_nc, s_dc);
   const int HW = s.H * s.W, W = s.W, k = s.k;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
@@ -241,7 +258,7 @@ __global__ void __launch_bounds__(kSubThreads) subpix_adj_kernel(Group g) {
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
         MassState m;
-        mass_eval<MASS, true>(c, x, y, m);
+        mass_eval<MASS, true>(c, s_c, s_nc, s_dc, x, y, m);
         float gx, gy;
         sersic_adj(c.src, m.sdx, m.sdy, sb, acc + A_SRC, gx, gy);
         if (NMAX >= 0) {

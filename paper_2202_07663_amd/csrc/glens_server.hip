@@ -9,6 +9,9 @@
 //      per kernel, so work of systems that arrived at different times overlaps on the GPU;
 //   3. retire systems that reached their step budget: evaluate log L, pick the best
 //      particle, record the result with its timestamps, free its memory.
+// Admission also keeps the active systems' sub-pixel work per step near what fills the GPU
+// (fill_subpixels): large systems then run close to first-come-first-served, which keeps
+// latency low, while small systems are batched into shared launches.
 // A system's arithmetic (work split, summation orders, random starts) depends only on its
 // own request, so its result is the same whether it runs alone or in a mix.
 #include <hip/hip_runtime.h>
@@ -45,6 +48,7 @@ struct Request {
   FitParams fp;
   std::vector<Prior> priors;
   size_t bytes = 0;
+  double work = 0.0;  // sub-pixel evaluations per step
   uint64_t t_submit = 0;
 };
 
@@ -56,6 +60,10 @@ struct Active {
   int tiles = 1;
   uint64_t t_admit = 0;
 };
+
+static double request_work(const ModelCfg& c, int P) {
+  return double(P) * c.H * c.W * c.k * c.k;
+}
 
 static size_t request_bytes(const ModelCfg& c, int P) {
   const int HW = c.H * c.W;
@@ -82,6 +90,7 @@ struct gl_server {
   // stats (guarded by mu)
   gl_server_stats st{};
   std::vector<std::unique_ptr<Active>> active;  // scheduler thread only
+  double active_work = 0.0;                      // scheduler thread only
   int thread_error = 0;
 };
 
@@ -118,6 +127,7 @@ static int admit(gl_server* s, std::unique_ptr<Request> rq) {
     r.t_submit = a->req->t_submit;
     r.t_admit = a->t_admit;
     r.t_done = now_ns();
+    s->active_work -= a->req->work;
     release(*a);
     finish(s, *a, r);
     return rc;
@@ -164,6 +174,8 @@ static void tick(gl_server* s) {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->queue.empty() || int(s->active.size()) >= s->opts.max_systems) break;
       if (s->st.hbm_in_use + s->queue.front()->bytes > s->opts.hbm_budget_bytes) break;
+      if (!s->active.empty() && s->active_work + s->queue.front()->work > s->opts.fill_subpixels)
+        break;
       rq = std::move(s->queue.front());
       s->queue.pop_front();
       s->st.hbm_in_use += rq->bytes;
@@ -171,6 +183,7 @@ static void tick(gl_server* s) {
       s->st.admitted++;
       s->st.queued = int(s->queue.size());
     }
+    s->active_work += rq->work;
     admit(s, std::move(rq));
   }
   if (s->active.empty()) return;
@@ -190,6 +203,7 @@ static void tick(gl_server* s) {
   if (!fin.empty() && run_grouped(s, fin, 1)) s->thread_error = 1;
   if (hipStreamSynchronize(s->stream) != hipSuccess) s->thread_error = 1;
   for (Active* a : fin) {
+    s->active_work -= a->req->work;
     gl_fit_result r;
     std::memset(&r, 0, sizeof(r));
     int rc = fit_result_from_device(a->fb, a->ws, a->req->fp.P, a->req->cfg, s->stream, &r);
@@ -235,6 +249,7 @@ int gl_server_create(const gl_server_opts* o, gl_server** out) {
   gl_server* s = new (std::nothrow) gl_server();
   if (!s) return set_error(GL_E_NOMEM, "host allocation failed");
   s->opts = *o;
+  if (!(s->opts.fill_subpixels > 0.0)) s->opts.fill_subpixels = 6e7;
   if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
     delete s;
     return set_error(GL_E_DEVICE, "cannot create the server stream");
@@ -274,6 +289,7 @@ int gl_submit(gl_server* s, const gl_model_desc* desc, const gl_fit_opts* o, uin
   rq->desc.obs = rq->obs.data();
   rq->fp = fit_params(o);
   rq->bytes = request_bytes(c, o->P);
+  rq->work = request_work(c, o->P);
   if (rq->bytes > s->opts.hbm_budget_bytes)
     return set_error(GL_E_BUDGET, "request needs %zu bytes, budget is %zu", rq->bytes,
                      s->opts.hbm_budget_bytes);

@@ -15,6 +15,7 @@ constexpr float kMassEpsMax = 0.6f;
 constexpr float kLightEpsMax = 0.9f;
 constexpr float kSieClosedMin = 0.1f;  // SIE closed form for |eps| >= this, series below
 constexpr double kSeriesTol = 1e-10;   // EPL series truncation, relative (far below FP32)
+constexpr double kSeriesTolDeriv = 1e-7;  // truncation of the derivative series (adjoint)
 
 // Accumulator slots of the adjoint (per particle, summed over sub-pixels).
 enum AccSlot {
@@ -47,6 +48,7 @@ struct LightC {
 // lane of that particle.
 struct PConst {
   int nterms;          // EPL / SIE series terms
+  int nterms_d;        // terms of the derivative series (adjoint), <= nterms
   int sie_closed;      // SIE: 1 = closed form, 0 = series
   // FP64 part: positions and the deflection are evaluated in double precision, because the
   // ray-traced source offset beta - x_s must be accurate to far below the FP32 resolution
@@ -71,7 +73,8 @@ struct PConst {
   LightC lens, src;
   float beta, inv_beta;
   float shp[kMaxShp];  // c_k / (beta sqrt(pi))
-  float dc[kMaxTerms]; // d c_n / dt
+  float dc[kMaxTerms]; // d c_n / dt (zero from nterms_d on)
+  float nc[kMaxTerms]; // (n + 1) c_{n+1}: coefficients of dS/dy (zero from nterms_d - 1 on)
 };
 
 // Prior / bijector of one parameter (the fit).

@@ -44,7 +44,8 @@ def test_result_same_alone_and_in_the_mix(G):
         srv = G.Server(hbm_budget_bytes=4 << 30, max_systems=1, steps_per_tick=5)
         alone.append(srv.wait(_submit(srv, case)))
         srv.close()
-    srv = G.Server(hbm_budget_bytes=4 << 30, max_systems=4, steps_per_tick=3)
+    srv = G.Server(hbm_budget_bytes=4 << 30, max_systems=4, steps_per_tick=3,
+                   fill_subpixels=1e12)
     tickets = [_submit(srv, c) for c in MIX]
     mixed = [srv.wait(t) for t in tickets]
     st = srv.stats()
@@ -75,7 +76,8 @@ def test_small_budget_forces_queueing(G):
     """A budget that holds one of these systems at a time: everything still completes, in
     order, and device memory in use never exceeds the budget."""
     case = MIX[0]
-    srv = G.Server(hbm_budget_bytes=6 << 20, max_systems=8, steps_per_tick=4)
+    srv = G.Server(hbm_budget_bytes=6 << 20, max_systems=8, steps_per_tick=4,
+                   fill_subpixels=1e12)
     tickets = [_submit(srv, case, K=8, seed=i) for i in range(4)]
     res = [srv.wait(t) for t in tickets]
     st = srv.stats()
