@@ -289,11 +289,17 @@ int launch_finalize(const Group& g, hipStream_t st) {
 
 size_t conv_lds_bytes(int H, int W, int K, int mode) {
   const int nstrip = (H + kConvRows - 1) / kConvRows;
-  const size_t np = size_t(nstrip * kConvRows + K - 1) * (W + K - 1);
-  return sizeof(float) * np * (mode == 2 ? 2 : 1);
+  const size_t np = size_t((nstrip * kConvRows + K - 1) | 1) * (W + K - 1);
+  (void)mode;
+  return sizeof(float) * np;
 }
 
 int launch_conv(int K, const Group& g, size_t lds, hipStream_t st) {
+  for (int i = 0; i < g.nsys; ++i) {
+    const int nstrip = (g.sys[i].H + kConvRows - 1) / kConvRows;
+    if (nstrip * g.sys[i].W > kConvMaxStrips * kConvThreads)
+      return set_error(GL_E_UNIMPLEMENTED, "image too large for the PSF kernel");
+  }
   static std::once_flag once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(once, [] {

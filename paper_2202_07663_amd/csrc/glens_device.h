@@ -80,8 +80,9 @@ GL_HD void decode_light(const float* th, LightC& L) {
   L.qb = float(-4.0 * e2 * den);
   L.qc = float((1.0 + ee + 2.0 * e1) * den);
   L.inv2n = float(0.5 / n);
-  L.lnre_n = float(log(re) / n);
+  L.l2re_n = float(log2(re) / n);
   L.bn = float(1.9992 * n - 0.3271);
+  L.bnl = float((1.9992 * n - 0.3271) * 1.4426950408889634);
   L.n = float(n);
   L.re = float(re);
   L.e1 = float(e1);
@@ -199,6 +200,17 @@ __device__ __forceinline__ double rcp_f64(double x) {
   return fma(fma(-x, r, 1.0), r, r);
 }
 __host__ inline double rcp_f64(double x) { return 1.0 / x; }
+
+// Single-precision hardware transcendentals in base 2 (about 1 ulp), for normal, finite
+// arguments; callers fold log2(e) into their per-particle constants.
+__device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
+__host__ inline float exp2_f32(float x) { return exp2f(x); }
+__device__ __forceinline__ float log2_f32(float x) { return __builtin_amdgcn_logf(x); }
+__host__ inline float log2_f32(float x) { return log2f(x); }
+__device__ __forceinline__ float rcp_f32(float x) { return __builtin_amdgcn_rcpf(x); }
+__host__ inline float rcp_f32(float x) { return 1.0f / x; }
+constexpr float kLn2f = 0.69314718055994531f;
+constexpr float kLog2e = 1.44269504088896341f;
 
 GL_HD double log_f64(double x) {
   int e;
@@ -417,8 +429,9 @@ struct LightEval {
 GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
   float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
   q = q < kR2Floor ? kR2Floor : q;
-  const float rho = expf(L.inv2n * logf(q) - L.lnre_n);
-  return L.i0 * expf(L.bn * (1.0f - rho));
+  // rho = (R / R_eff)^(1/n) = 2^(log2(R^2) / (2n) - log2(R_eff) / n);  I = I0 e^(b_n (1 - rho))
+  const float rho = exp2_f32(fmaf(log2_f32(q), L.inv2n, -L.l2re_n));
+  return L.i0 * exp2_f32(fmaf(-L.bnl, rho, L.bnl));
 }
 
 // Intensity plus the accumulator terms (weight sb) and d I / d(dx, dy).
@@ -427,11 +440,12 @@ GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc
   float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
   const bool fl = q < kR2Floor;
   q = fl ? kR2Floor : q;
-  const float lnrho = L.inv2n * logf(q) - L.lnre_n;
-  const float rho = expf(lnrho);
-  const float E = expf(L.bn * (1.0f - rho));
+  const float l2rho = fmaf(log2_f32(q), L.inv2n, -L.l2re_n);
+  const float lnrho = kLn2f * l2rho;
+  const float rho = exp2_f32(l2rho);
+  const float E = exp2_f32(fmaf(-L.bnl, rho, L.bnl));
   const float I = L.i0 * E;
-  const float IQ = fl ? 0.0f : -I * L.bn * rho * L.inv2n / q;
+  const float IQ = fl ? 0.0f : -I * L.bn * rho * L.inv2n * rcp_f32(q);
   gdx = IQ * (2.0f * L.qa * dx + L.qb * dy);
   gdy = IQ * (L.qb * dx + 2.0f * L.qc * dy);
   const float sI = sb * I, sIQ = sb * IQ, r2q = dx * dx + dy * dy + q;
@@ -477,7 +491,7 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
     for (int n2 = 0; n2 <= NMAX - n1; ++n2) T = fmaf(c.shp[shp_index(n1, n2)], hv[n2], T);
     U = fmaf(hu[n1], T, U);
   }
-  return expf(-0.5f * (u * u + v * v)) * U;
+  return exp2_f32(-0.5f * kLog2e * (u * u + v * v)) * U;
 }
 
 // Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y), using
@@ -494,7 +508,7 @@ GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float*
   float hu[NMAX + 1], hv[NMAX + 1];
   hermite<NMAX>(u, hu);
   hermite<NMAX>(v, hv);
-  const float G = expf(-0.5f * (u * u + v * v));
+  const float G = exp2_f32(-0.5f * kLog2e * (u * u + v * v));
   const float sg = sb * G;
   float U = 0.f, Uu = 0.f, Uv = 0.f;
 #pragma unroll

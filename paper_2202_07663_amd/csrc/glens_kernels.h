@@ -22,6 +22,7 @@ namespace glens {
 constexpr int kSubThreads = 256;
 constexpr int kConvThreads = 256;
 constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
+constexpr int kConvMaxStrips = 8;  // strips per lane: (H/8 rounded up) * W <= 8 * 256
 
 // --- bijectors (Sec. 2.2): exp for log-normal priors, sigmoid onto (lo, hi) for truncated
 // normal and uniform priors, identity for normal priors ---
@@ -126,8 +127,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return tot;  // valid on lane 0 of wave 0
 }
 
+// The padded image sits in LDS column-major (column pitch Hs, odd so that the lanes of a wave,
+// which own consecutive columns, hit distinct banks). A lane's strip of kConvRows output rows
+// in column j reads, per tap column b, kConvRows + K - 1 consecutive words at immediate
+// offsets from one base address.
 template <int K>
-__device__ __forceinline__ void correlate_strip(const float* __restrict__ buf, int Wp, int i0,
+__device__ __forceinline__ void correlate_strip(const float* __restrict__ buf, int Hs, int i0,
                                                 int j, const float* __restrict__ taps,
                                                 float* acc) {
   constexpr int R = kConvRows;
@@ -135,9 +140,10 @@ __device__ __forceinline__ void correlate_strip(const float* __restrict__ buf, i
   for (int r = 0; r < R; ++r) acc[r] = 0.f;
 #pragma unroll 1
   for (int b = 0; b < K; ++b) {
+    const float* colp = buf + (j + b) * Hs + i0;
     float col[R + K - 1];
 #pragma unroll
-    for (int rr = 0; rr < R + K - 1; ++rr) col[rr] = buf[(i0 + rr) * Wp + j + b];
+    for (int rr = 0; rr < R + K - 1; ++rr) col[rr] = colp[rr];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
       const float kv = taps[a * K + b];
@@ -157,28 +163,34 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
   constexpr int R = kConvRows, C = (K - 1) / 2;
   const int H = s.H, W = s.W, HW = H * W;
   const int nstrip = (H + R - 1) / R;
-  const int Hp = nstrip * R + K - 1, Wp = W + K - 1, NP = Hp * Wp;
+  const int Hs = (nstrip * R + K - 1) | 1, Wp = W + K - 1, NP = Hs * Wp;
   const int mode = s.mode;
-  float* A = lds;
-  float* Bm = lds + NP;
+  float* A = lds;  // padded image; in the adjoint pass it holds the padded pixel seed
   const float* m0 = s.m0 + (size_t)part * HW;
-  for (int idx = threadIdx.x; idx < NP; idx += blockDim.x) {
-    const int r = idx / Wp, q = idx - r * Wp;
-    const int i = r - C, j = q - C;
-    A[idx] = (i >= 0 && i < H && j >= 0 && j < W) ? m0[i * W + j] : 0.f;
-    if (mode == 2) Bm[idx] = 0.f;
+  for (int idx = threadIdx.x; idx < NP; idx += blockDim.x) A[idx] = 0.f;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {  // coalesced global read
+    const int i = idx / W, j = idx - i * W;
+    A[(j + C) * Hs + i + C] = m0[idx];
   }
   __syncthreads();
   double ll = 0.0, c2 = 0.0;
   const float* obs = s.obs;
-  for (int sidx = threadIdx.x; sidx < nstrip * W; sidx += blockDim.x) {
+  // A lane owns at most kConvMaxStrips strips (checked on the host); their pixel seeds stay
+  // in registers until every lane has finished reading the image.
+  float seed[kConvMaxStrips][R];
+#pragma unroll
+  for (int t = 0; t < kConvMaxStrips; ++t) {
+    const int sidx = threadIdx.x + t * blockDim.x;
+    if (sidx >= nstrip * W) break;
     const int st = sidx / W, j = sidx - st * W, i0 = st * R;
     float acc[R];
-    correlate_strip<K>(A, Wp, i0, j, s.psf_flip, acc);
+    correlate_strip<K>(A, Hs, i0, j, s.psf_flip, acc);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = i0 + r;
-      if (i >= H) break;
+      seed[t][r] = 0.f;
+      if (i >= H) continue;
       const float m = acc[r];
       if (mode == 0) {
         s.img[(size_t)part * HW + i * W + j] = m;
@@ -186,14 +198,12 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
         const float pos = m > 0.f ? m : 0.f;
         const float s2 = s.s2b + pos * s.inv_gt;
         const float res = obs[i * W + j] - m;
-        const float is2 = 1.0f / s2;
+        const float is2 = rcp_f32(s2);
         const float chi = res * res * is2;
         c2 += double(chi);
-        ll += double(chi + logf(6.283185307179586f * s2));
-        if (mode == 2) {
-          const float sp = m > 0.f ? s.inv_gt : 0.f;
-          Bm[(i + C) * Wp + j + C] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
-        }
+        ll += double(chi + kLn2f * log2_f32(6.283185307179586f * s2));
+        const float sp = m > 0.f ? s.inv_gt : 0.f;
+        seed[t][r] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
       }
     }
   }
@@ -208,12 +218,25 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
     if (threadIdx.x == 0) s.chi2[part] = ctot;
   }
   if (mode != 2) return;
+  __syncthreads();  // every lane is done with the image: overwrite its interior with the seed
+#pragma unroll
+  for (int t = 0; t < kConvMaxStrips; ++t) {
+    const int sidx = threadIdx.x + t * blockDim.x;
+    if (sidx >= nstrip * W) break;
+    const int st = sidx / W, j = sidx - st * W, i0 = st * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (i0 + r < H) A[(j + C) * Hs + i0 + r + C] = seed[t][r];
+  }
   __syncthreads();
   // d logL / d m0 = correlation of the pixel seed with the (unflipped) PSF
-  for (int sidx = threadIdx.x; sidx < nstrip * W; sidx += blockDim.x) {
+#pragma unroll
+  for (int t = 0; t < kConvMaxStrips; ++t) {
+    const int sidx = threadIdx.x + t * blockDim.x;
+    if (sidx >= nstrip * W) break;
     const int st = sidx / W, j = sidx - st * W, i0 = st * R;
     float acc[R];
-    correlate_strip<K>(Bm, Wp, i0, j, s.psf, acc);
+    correlate_strip<K>(A, Hs, i0, j, s.psf, acc);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = i0 + r;
@@ -232,7 +255,8 @@ constexpr int n_slots() {
 }
 
 template <int MASS, int NMAX>
-__global__ void __launch_bounds__(kSubThreads) subpix_adj_kernel(Group g) {
+__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3)))
+subpix_adj_kernel(Group g) {
   constexpr int NS = n_slots<NMAX>();
   __shared__ double red[kSubThreads / 64][NS];
   const int si = find_sys(g, blockIdx.x);

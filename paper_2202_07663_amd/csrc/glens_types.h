@@ -36,8 +36,9 @@ static_assert(A_SHP_C + kMaxShp <= kNAcc, "accumulator slots");
 struct LightC {
   float qa, qb, qc;    // R^2 = qa dx^2 + qb dx dy + qc dy^2
   float inv2n;         // 1 / (2n)
-  float lnre_n;        // ln(R_eff) / n
+  float l2re_n;        // log2(R_eff) / n
   float bn, i0;        // b_n = 1.9992 n - 0.3271, I0
+  float bnl;           // b_n log2(e)
   float n, re;         // Sersic index, R_eff
   float e1, e2;        // clamped eccentricities
   float inv1me2;       // 1 / (1 - |eps|^2)
