@@ -181,6 +181,69 @@ int gl_fit_state_store(gl_fit_state* st, float* z, float* m, float* v, int* step
 int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Preconditioned Hamiltonian Monte Carlo (Sec. 2.5): `chains` independent chains on the
+ * posterior in unconstrained space, log p~(z | I) = log L(g(z)) + log p~(z) (the fit's
+ * target), momenta p ~ N(0, M) for a mass matrix M given by its inverse (the paper sets M
+ * to the inverse of the variational posterior covariance, so M^-1 is that covariance),
+ * H = -log p~(z | I) + p^T M^-1 p / 2, L leapfrog steps of size eps per trajectory and a
+ * Metropolis accept with probability min(1, exp(H0 - H1)). Any non-finite log posterior
+ * along a trajectory rejects it. During the first floor(adapt_frac n_burn) trajectories eps
+ * follows dual averaging (Hoffman & Gelman 2014, gamma 0.05, t0 10, kappa 0.75,
+ * mu = log(10 step_size)) of the chain-mean acceptance probability towards target_accept
+ * (the paper: 0.75 over the first 80% of burn-in); it then stays at the averaged value.
+ * Every chain is one particle of the likelihood pipeline: a leapfrog step is one batched
+ * gradient launch over all chains. Random numbers: Philox4x32-10 keyed by `seed`, counter
+ * (chain, parameter, trajectory, purpose).
+ * ------------------------------------------------------------------------------------- */
+typedef struct gl_hmc_opts {
+  int chains;                  /* >= 1 */
+  int n_leapfrog;              /* L, >= 1 */
+  int n_burn, n_samples;       /* trajectories discarded / recorded, >= 0 */
+  float step_size;             /* initial eps, > 0 */
+  float target_accept;         /* in (0, 1) */
+  float adapt_frac;            /* share of burn-in with step-size adaptation, in [0, 1] */
+  uint64_t seed;
+  const float* inv_mass;       /* host, copied: M^-1, NULL for the identity; the diagonal [d]
+                                  (> 0) or, with inv_mass_dense, the full symmetric positive
+                                  definite [d][d] row-major (e.g. a posterior covariance of z) */
+  int inv_mass_dense;
+  const gl_prior* priors;      /* host [d], copied */
+} gl_hmc_opts;
+
+typedef struct gl_hmc_info {
+  float step_size;       /* current eps (the averaged one once adaptation ended) */
+  double accept_mean;    /* mean acceptance probability over the recorded trajectories */
+  int trajectories;      /* trajectories run so far */
+} gl_hmc_info;
+
+typedef struct gl_hmc gl_hmc;
+/* Create the sampler on `model` (which must hold an observed image) and evaluate the
+ * gradient at the starts. Positions are kept in FP64 (the likelihood sees them rounded to
+ * FP32); momenta in FP32. z0: device [chains][d] FP64 unconstrained starts (copied), or
+ * NULL to draw them from the prior. GL_E_INVALID for bad options or an inv_mass that is
+ * not symmetric positive definite. The state holds device arrays of
+ * ((5 + n_samples) chains d + 2 d^2) floats; it uses the model's workspace, so the model
+ * must outlive it and not be used concurrently from another stream. */
+int gl_hmc_create(gl_model* model, const gl_hmc_opts* opts, const double* z0, gl_hmc** out,
+                  void* stream);
+int gl_hmc_destroy(gl_hmc* h);
+/* Run the next `n` trajectories (burn-in first, then recorded ones) on `stream` (not
+ * blocking). GL_E_INVALID if fewer than n are left of n_burn + n_samples. */
+int gl_hmc_run(gl_hmc* h, int n, void* stream);
+/* Copy the recorded samples, physical parameters g(z), to theta: device
+ * [n_samples][chains][d] FP32 (rows not yet recorded hold unspecified values). */
+int gl_hmc_samples(gl_hmc* h, float* theta, void* stream);
+/* Step size, mean acceptance and progress (blocking). */
+int gl_hmc_get_info(gl_hmc* h, gl_hmc_info* out, void* stream);
+/* L leapfrog steps of size eps (no momentum draw, no accept, no adaptation) from caller
+ * positions z (device [chains][d] FP64) and momenta p (device [chains][d] FP32), writing
+ * the end point to z_out (FP64), p_out (FP32) and log p~(z_L | I) to logpost_out (device
+ * [chains] FP64). The sampler's own chain state is overwritten; use a separate gl_hmc for
+ * this. */
+int gl_hmc_leapfrog(gl_hmc* h, const double* z, const float* p, int L, float eps,
+                    double* z_out, float* p_out, double* logpost_out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Continuous-batching server: systems of mixed sizes and component sets are admitted as
  * slots and HBM budget free up; each tick advances every active system by
  * steps_per_tick Adam steps, with the systems of one kernel configuration sharing one

@@ -1,0 +1,124 @@
+"""FP64 oracle of the preconditioned Hamiltonian Monte Carlo step (TEST INFRASTRUCTURE ONLY).
+
+Sec. 2.5: sampling in unconstrained space with target log p~(z | I_obs) = log L(g(z)) +
+log p~(z); momenta p ~ N(0, M), where the paper takes M as the inverse of the variational
+posterior covariance (here inv_mass = M^-1, diagonal or dense);
+Hamiltonian H = -log p~(z | I) + p^T M^-1 p / 2; leapfrog integration with step eps and
+L steps; Metropolis acceptance min(1, exp(H0 - H1)). The step size is tuned by the dual
+averaging of Hoffman & Gelman (2014, Sec. 3.2) towards a target acceptance probability
+(0.75 in the paper) during the first part of burn-in.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .fit import objective_and_grad
+
+
+def _apply_inv_mass(inv_mass, p):
+    """M^-1 p for rows p: inv_mass is the diagonal [d] or the full symmetric matrix [d, d]."""
+    inv_mass = np.asarray(inv_mass, np.float64)
+    if inv_mass.ndim == 2:
+        return p @ inv_mass.T
+    return inv_mass * p
+
+
+def kinetic(p, inv_mass):
+    """p^T M^-1 p / 2 per row."""
+    p = np.asarray(p, np.float64)
+    return 0.5 * np.sum(p * _apply_inv_mass(inv_mass, p), axis=-1)
+
+
+def leapfrog_fn(fg, z, p, eps, L, inv_mass):
+    """L leapfrog steps of size eps for H = f(z) + p^T M^-1 p / 2, where fg(z) returns f and
+    its gradient (rows are independent chains) and M^-1 is diagonal ([d]) or dense ([d, d]):
+    a half kick, then L drifts separated by full kicks, and a final half kick.
+    Returns z_L, p_L, f(z_0), f(z_L)."""
+    z = np.array(z, np.float64)
+    p = np.array(p, np.float64)
+    f0, gf = fg(z)
+    f = f0
+    p = p - 0.5 * eps * gf
+    for step in range(L):
+        z = z + eps * _apply_inv_mass(inv_mass, p)
+        f, gf = fg(z)
+        p = p - (eps if step < L - 1 else 0.5 * eps) * gf
+    return z, p, f0, f
+
+
+def leapfrog(model, z, p, eps, L, obs, priors, inv_mass):
+    """Leapfrog on the lens posterior in unconstrained space: f = -log p~(z | I)."""
+    return leapfrog_fn(lens_objective(model, obs, priors), z, p, eps, L, inv_mass)
+
+
+def hamiltonian(f, p, inv_mass):
+    return f + kinetic(p, inv_mass)
+
+
+def accept_probability(h0, h1):
+    dh = np.asarray(h0) - np.asarray(h1)
+    with np.errstate(over="ignore", invalid="ignore"):
+        a = np.minimum(1.0, np.exp(dh))
+    return np.where(np.isfinite(a), a, 0.0)
+
+
+class DualAveraging:
+    """Hoffman & Gelman (2014), Sec. 3.2: H_m = (1 - 1/(m + t0)) H_{m-1} + (delta - a_m)/(m + t0);
+    log eps_m = mu - sqrt(m)/gamma H_m; log eps_bar_m = m^-kappa log eps_m
+    + (1 - m^-kappa) log eps_bar_{m-1}; mu = log(10 eps_0)."""
+
+    def __init__(self, eps0, target=0.75, gamma=0.05, t0=10.0, kappa=0.75):
+        self.mu = math.log(10.0 * eps0)
+        self.target, self.gamma, self.t0, self.kappa = target, gamma, t0, kappa
+        self.h = 0.0
+        self.log_eps_bar = 0.0
+        self.m = 0
+        self.eps = eps0
+
+    def update(self, accept):
+        self.m += 1
+        m = self.m
+        w = 1.0 / (m + self.t0)
+        self.h = (1.0 - w) * self.h + w * (self.target - accept)
+        log_eps = self.mu - math.sqrt(m) / self.gamma * self.h
+        eta = m ** (-self.kappa)
+        self.log_eps_bar = eta * log_eps + (1.0 - eta) * self.log_eps_bar
+        self.eps = math.exp(log_eps)
+        return self.eps
+
+    def final(self):
+        return math.exp(self.log_eps_bar)
+
+
+def hessian_fd(fg, z, h=1e-4):
+    """Hessian of f at one point z [d] by central differences of the exact gradient,
+    symmetrised. All 2 d perturbed points go through fg as one batch."""
+    z = np.asarray(z, np.float64)
+    d = z.size
+    pts = np.repeat(z[None, :], 2 * d, axis=0)
+    pts[np.arange(d), np.arange(d)] += h
+    pts[d + np.arange(d), np.arange(d)] -= h
+    _, g = fg(pts)
+    hess = (g[:d] - g[d:]) / (2 * h)
+    return 0.5 * (hess + hess.T)
+
+
+def newton_mode(fg, z0, iters=6, h=1e-4):
+    """Posterior mode by Newton's method on f from a start in its basin; returns the mode
+    and the Hessian there (the Laplace approximation's precision matrix)."""
+    z = np.asarray(z0, np.float64).copy()
+    for _ in range(iters):
+        _, g = fg(z[None, :])
+        hess = hessian_fd(fg, z, h)
+        z = z - np.linalg.solve(hess, g[0])
+    return z, hessian_fd(fg, z, h)
+
+
+def lens_objective(model, obs, priors):
+    """fg(z) -> (f, d f / d z) for the lens posterior in unconstrained space."""
+    def fg(zz):
+        f, g, _ = objective_and_grad(model, zz, obs, priors)
+        return f, g
+    return fg

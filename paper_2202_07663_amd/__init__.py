@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import GlError, check, lib
 
-__all__ = ["Model", "LogLik", "FitState", "fit", "Server", "GlError", "param_names", "nparams",
+__all__ = ["Model", "LogLik", "FitState", "fit", "HMC", "Server", "GlError", "param_names", "nparams",
            "make_priors", "make_fit_opts", "result_dict"]
 
 
@@ -258,6 +258,86 @@ def fit(model: Model, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0, stream
     r = _lib.FitResult()
     check(lib().gl_fit(model._h, ctypes.byref(opts), ctypes.byref(r), _stream_ptr(stream)))
     return result_dict(r)
+
+
+# ------------------------------------------------------------------------------------------
+# Preconditioned Hamiltonian Monte Carlo (Sec. 2.5)
+# ------------------------------------------------------------------------------------------
+class HMC:
+    """`chains` HMC chains on the posterior of one system in unconstrained space, run by the
+    library's kernels (one batched likelihood-gradient launch per leapfrog step).
+    z0: optional [chains, d] unconstrained starts (e.g. the fit's best particle plus
+    jitter; kept in FP64); inv_mass: optional inverse mass matrix M^-1, the diagonal [d] or the full
+    [d, d] (the paper uses the variational posterior covariance of z)."""
+
+    def __init__(self, model: Model, chains: int, n_leapfrog: int, n_burn: int, n_samples: int,
+                 priors, step_size: float = 1e-2, target_accept: float = 0.75,
+                 adapt_frac: float = 0.8, seed: int = 0, z0: torch.Tensor | None = None,
+                 inv_mass=None, stream=None):
+        assert len(priors) == model.d
+        self.model, self.C = model, chains
+        self.n_burn, self.n_samples = n_burn, n_samples
+        self._pa = make_priors(priors)
+        o = _lib.HmcOpts(chains=chains, n_leapfrog=n_leapfrog, n_burn=n_burn,
+                         n_samples=n_samples, step_size=step_size, target_accept=target_accept,
+                         adapt_frac=adapt_frac, seed=seed, priors=self._pa)
+        if inv_mass is not None:
+            im = np.ascontiguousarray(np.asarray(inv_mass, np.float32))
+            assert im.shape in ((model.d,), (model.d, model.d))
+            self._im = (ctypes.c_float * im.size)(*im.ravel().tolist())
+            o.inv_mass = self._im
+            o.inv_mass_dense = int(im.ndim == 2)
+        zp = None
+        if z0 is not None:
+            z0 = z0.to(torch.float64).contiguous()
+            assert z0.is_cuda and z0.shape == (chains, model.d)
+            zp = z0.data_ptr()
+        h = ctypes.c_void_p()
+        check(lib().gl_hmc_create(model._h, ctypes.byref(o), zp, ctypes.byref(h),
+                                  _stream_ptr(stream)))
+        self._h = h
+
+    def run(self, n: int | None = None, stream=None):
+        """Run the next n trajectories (all that are left by default)."""
+        if n is None:
+            n = self.n_burn + self.n_samples - self.info(stream)["trajectories"]
+        check(lib().gl_hmc_run(self._h, n, _stream_ptr(stream)))
+
+    def samples(self, stream=None) -> torch.Tensor:
+        """[n_samples, chains, d] physical parameters of the recorded trajectories."""
+        out = torch.empty((self.n_samples, self.C, self.model.d), dtype=torch.float32,
+                          device="cuda")
+        check(lib().gl_hmc_samples(self._h, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def info(self, stream=None) -> dict:
+        r = _lib.HmcInfo()
+        check(lib().gl_hmc_get_info(self._h, ctypes.byref(r), _stream_ptr(stream)))
+        return {"step_size": r.step_size, "accept_mean": r.accept_mean,
+                "trajectories": r.trajectories}
+
+    def leapfrog(self, z: torch.Tensor, p: torch.Tensor, L: int, eps: float, stream=None):
+        """L leapfrog steps from (z, p) (no accept): returns z_L (FP64), p_L (FP32) and
+        log p~(z_L | I)."""
+        z, p = z.to(torch.float64).contiguous(), p.to(torch.float32).contiguous()
+        for t in (z, p):
+            assert t.is_cuda and t.shape == (self.C, self.model.d)
+        zo, po = torch.empty_like(z), torch.empty_like(p)
+        lp = torch.empty(self.C, dtype=torch.float64, device="cuda")
+        check(lib().gl_hmc_leapfrog(self._h, z.data_ptr(), p.data_ptr(), L, eps, zo.data_ptr(),
+                                    po.data_ptr(), lp.data_ptr(), _stream_ptr(stream)))
+        return zo, po, lp
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_hmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------------------------

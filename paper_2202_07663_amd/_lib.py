@@ -52,6 +52,19 @@ class FitResult(ctypes.Structure):
                 ("t_done", ctypes.c_uint64)]
 
 
+class HmcOpts(ctypes.Structure):
+    _fields_ = [("chains", ctypes.c_int), ("n_leapfrog", ctypes.c_int), ("n_burn", ctypes.c_int),
+                ("n_samples", ctypes.c_int), ("step_size", ctypes.c_float),
+                ("target_accept", ctypes.c_float), ("adapt_frac", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("inv_mass", ctypes.POINTER(ctypes.c_float)),
+                ("inv_mass_dense", ctypes.c_int), ("priors", ctypes.POINTER(Prior))]
+
+
+class HmcInfo(ctypes.Structure):
+    _fields_ = [("step_size", ctypes.c_float), ("accept_mean", ctypes.c_double),
+                ("trajectories", ctypes.c_int)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_systems", ctypes.c_int),
                 ("steps_per_tick", ctypes.c_int), ("fill_subpixels", ctypes.c_double)]
@@ -81,6 +94,12 @@ _SIGNATURES = {
     "gl_fit_state_load": [_vp, _vp, _vp, _vp, _i, _vp],
     "gl_fit_state_store": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i), _vp],
     "gl_fit_state_result": [_vp, ctypes.POINTER(FitResult), _vp],
+    "gl_hmc_create": [_vp, ctypes.POINTER(HmcOpts), _vp, ctypes.POINTER(_vp), _vp],
+    "gl_hmc_destroy": [_vp],
+    "gl_hmc_run": [_vp, _i, _vp],
+    "gl_hmc_samples": [_vp, _vp, _vp],
+    "gl_hmc_get_info": [_vp, ctypes.POINTER(HmcInfo), _vp],
+    "gl_hmc_leapfrog": [_vp, _vp, _vp, _i, ctypes.c_float, _vp, _vp, _vp, _vp],
     "gl_server_create": [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)],
     "gl_server_destroy": [_vp],
     "gl_submit": [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(FitOpts),

@@ -1,0 +1,561 @@
+// Preconditioned Hamiltonian Monte Carlo over many chains (Sec. 2.5): the gl_hmc* C ABI.
+//
+// Target: log p~(z | I) = log L(g(z)) + log p~(z) in unconstrained space (Sec. 2.2), with
+// the gradient from the likelihood pipeline plus the prior / bijector terms. Each chain
+// runs, per trajectory:
+//   p ~ N(0, M);  half kick, then L drifts z += eps M^-1 p separated by full kicks, and a
+//   final half kick (leapfrog);  accept with probability min(1, e^(H0 - H1)),
+//   H = -log p~(z | I) + p^T M^-1 p / 2.
+// M^-1 = S is given by its lower Cholesky factor S = C C^T (the paper takes M as the inverse
+// of the variational covariance, so C is that covariance's factor): p = C^-T n with
+// n ~ N(0, I), p^T S p / 2 = |C^T p|^2 / 2 and the drift applies C (C^T p).
+// During the first adapt_frac of burn-in the step size follows Hoffman & Gelman's dual
+// averaging towards target_accept (the paper uses 0.75 over the first 80% of burn-in); it
+// is then fixed at the averaged value. Every chain is one particle of the likelihood launch,
+// so a leapfrog step costs one batched gradient call over all chains. The per-chain kernels
+// run one 64-lane block per chain with the chain's d <= 68 coordinates in LDS. The
+// trajectory counter lives in device memory, so a trajectory's launches do not change
+// between trajectories.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "glens_device.h"
+#include "glens_fit.h"
+#include "glens_fit_device.h"
+#include "glens_host.h"
+
+namespace glens {
+
+constexpr int kHmcThreads = 64;
+
+struct HmcArgs {
+  int C, d;
+  int n_burn, n_adapt;
+  float target;
+  float eps_fixed;     // > 0: use this step size instead of the adapted one
+  const Prior* prior;
+  const float* chol;   // [d][d] row-major lower factor of M^-1
+  const float* chol_it;// [d][d] row-major (chol^-1)^T, upper triangular
+  int* traj;           // index of the current trajectory (device scalar)
+  double* z;           // [C][d] position (unconstrained), FP64 so that many small drifts
+                       // accumulate without rounding (posterior widths can be ~1e-6 of |z|)
+  float* z32;          // [C][d] FP32 copy of z read by the likelihood pipeline
+  float* p;            // [C][d] momentum
+  float* g;            // [C][d] d log p~(z | I) / dz
+  double* lp;          // [C] log p~(z | I)
+  double* zs;          // [C][d] trajectory start
+  float* gs;
+  double* lps;
+  double* k0;          // [C] kinetic energy at the start
+  int* bad;            // [C] a non-finite log posterior was met along the trajectory
+  const double* logl;  // [C] from the likelihood pipeline
+  const float* grad;   // [C][d] d log L / d theta from the pipeline
+  const float* theta;  // [C][d] g(z) from the prologue
+  float* eps;          // adapted step size (device scalar)
+  double* da;          // dual averaging: mu, h, log_eps_bar, m
+  float* accept;       // [C] acceptance probability of the last trajectory
+  double* stats;       // sum of the chain-mean acceptance over sampled trajectories, count
+  float* samples;      // [n_samples][C][d] physical parameters
+  uint32_t seed_lo, seed_hi;
+};
+
+__device__ __forceinline__ float step_size(const HmcArgs& a) {
+  return a.eps_fixed > 0.f ? a.eps_fixed : *a.eps;
+}
+
+// v = chol^T x for one chain (x in LDS, v to LDS); lanes own output coordinates.
+__device__ __forceinline__ void chol_t_times(const HmcArgs& a, const float* x, float* v) {
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    float s = 0.f;
+    for (int i = j; i < a.d; ++i) s += a.chol[i * a.d + j] * x[i];
+    v[j] = s;
+  }
+}
+
+// log p~(z | I) and its gradient from the pipeline outputs (one lane per chain).
+__global__ void __launch_bounds__(64) hmc_lp_grad_kernel(HmcArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.C) return;
+  const double ll = a.logl[c];
+  double lp = ll;
+  for (int j = 0; j < a.d; ++j) {
+    const size_t i = size_t(c) * a.d + j;
+    float dlp, dth;
+    lp += log_prior_z(a.prior[j], a.z32[i], a.theta[i], dlp, dth);
+    a.g[i] = a.grad[i] * dth + dlp;
+  }
+  if (!isfinite(lp)) {
+    lp = -INFINITY;
+    a.bad[c] = 1;
+    for (int j = 0; j < a.d; ++j) a.g[size_t(c) * a.d + j] = 0.f;
+  }
+  a.lp[c] = lp;
+}
+
+// New momentum p = chol^-T n, saved trajectory start and kinetic energy |n|^2 / 2.
+__global__ void __launch_bounds__(kHmcThreads) hmc_draw_kernel(HmcArgs a) {
+  __shared__ float s_n[kMaxParams];
+  const int c = blockIdx.x;
+  const int traj = *a.traj;
+  const size_t row = size_t(c) * a.d;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    uint32_t w[4] = {uint32_t(c), uint32_t(j), uint32_t(traj), 0x6d6f6d65u};
+    philox4x32_10(w, a.seed_lo, a.seed_hi);
+    const double u1 = u01(w[0], w[1]), u2 = u01(w[2], w[3]);
+    s_n[j] = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+    a.zs[row + j] = a.z[row + j];
+    a.gs[row + j] = a.g[row + j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.d; i += kHmcThreads) {
+    float s = 0.f;
+    for (int j = i; j < a.d; ++j) s += a.chol_it[i * a.d + j] * s_n[j];
+    a.p[row + i] = s;
+  }
+  if (threadIdx.x == 0) {
+    double k = 0.0;
+    for (int j = 0; j < a.d; ++j) k += 0.5 * double(s_n[j]) * s_n[j];
+    a.k0[c] = k;
+    a.lps[c] = a.lp[c];
+    a.bad[c] = 0;
+  }
+}
+
+// p += scale eps g; then, if drift, z += eps chol (chol^T p).
+__global__ void __launch_bounds__(kHmcThreads) hmc_move_kernel(HmcArgs a, float scale, int drift) {
+  __shared__ float s_p[kMaxParams], s_v[kMaxParams];
+  const int c = blockIdx.x;
+  const float eps = step_size(a);
+  const size_t row = size_t(c) * a.d;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    const float pn = a.p[row + j] + scale * eps * a.g[row + j];
+    a.p[row + j] = pn;
+    s_p[j] = pn;
+  }
+  if (!drift) return;
+  __syncthreads();
+  chol_t_times(a, s_p, s_v);
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    float s = 0.f;
+    for (int i = 0; i <= j; ++i) s += a.chol[j * a.d + i] * s_v[i];
+    const double zn = a.z[row + j] + double(eps) * s;
+    a.z[row + j] = zn;
+    a.z32[row + j] = float(zn);
+  }
+}
+
+// Metropolis accept / reject and the sample record.
+__global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
+  __shared__ float s_p[kMaxParams], s_v[kMaxParams];
+  __shared__ int s_keep;
+  const int c = blockIdx.x;
+  const int traj = *a.traj;
+  const size_t row = size_t(c) * a.d;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) s_p[j] = a.p[row + j];
+  __syncthreads();
+  chol_t_times(a, s_p, s_v);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double k1 = 0.0;
+    for (int j = 0; j < a.d; ++j) k1 += 0.5 * double(s_v[j]) * s_v[j];
+    const double h0 = -a.lps[c] + a.k0[c], h1 = -a.lp[c] + k1;
+    double acc = exp(fmin(0.0, h0 - h1));
+    if (a.bad[c] || !isfinite(h1) || !isfinite(acc)) acc = 0.0;
+    uint32_t w[4] = {uint32_t(c), 0xffffffffu, uint32_t(traj), 0x61636370u};
+    philox4x32_10(w, a.seed_lo, a.seed_hi);
+    const int keep = u01(w[0], w[1]) < acc;
+    if (!keep) a.lp[c] = a.lps[c];
+    a.accept[c] = float(acc);
+    s_keep = keep;
+  }
+  __syncthreads();
+  const int keep = s_keep;
+  float* out = a.samples && traj >= a.n_burn ? a.samples + (size_t(traj - a.n_burn) * a.C + c) * a.d
+                                             : nullptr;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    if (!keep) {
+      const double zj = a.zs[row + j];
+      a.z[row + j] = zj;
+      a.z32[row + j] = float(zj);
+      a.g[row + j] = a.gs[row + j];
+    }
+    if (out) out[j] = bijector_fwd(a.prior[j], a.z32[row + j]);
+  }
+}
+
+// Step-size adaptation (one lane, after every chain's accept): dual averaging on the
+// chain-mean acceptance probability; then the trajectory counter advances.
+__global__ void hmc_adapt_kernel(HmcArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int traj = *a.traj;
+  double mean = 0.0;
+  for (int c = 0; c < a.C; ++c) mean += a.accept[c];
+  mean /= a.C;
+  if (traj < a.n_adapt) {
+    const double t0 = 10.0, gamma = 0.05, kappa = 0.75;
+    const double m = a.da[3] + 1.0;
+    const double w = 1.0 / (m + t0);
+    const double h = (1.0 - w) * a.da[1] + w * (a.target - mean);
+    const double log_eps = a.da[0] - sqrt(m) / gamma * h;
+    const double eta = pow(m, -kappa);
+    a.da[1] = h;
+    a.da[2] = eta * log_eps + (1.0 - eta) * a.da[2];
+    a.da[3] = m;
+    *a.eps = float(traj + 1 == a.n_adapt ? exp(a.da[2]) : exp(log_eps));
+  }
+  if (traj >= a.n_burn) {
+    a.stats[0] += mean;
+    a.stats[1] += 1.0;
+  }
+  *a.traj = traj + 1;
+}
+
+// Starts drawn from the prior when the caller gives none.
+__global__ void __launch_bounds__(256) hmc_start_kernel(HmcArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.C * a.d) return;
+  const int c = i / a.d, j = i - c * a.d;
+  const float z = draw_start(a.prior[j], a.seed_lo ^ 0x5eedu, a.seed_hi, c, j);
+  a.z[i] = z;
+  a.z32[i] = z;
+}
+
+// FP32 copy of caller-supplied positions.
+__global__ void __launch_bounds__(256) hmc_round_kernel(HmcArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.C * a.d) a.z32[i] = float(a.z[i]);
+}
+
+}  // namespace glens
+
+using namespace glens;
+
+#define GL_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
+                       #call, hipGetErrorString(e_));                                    \
+  } while (0)
+
+struct gl_hmc {
+  gl_model* model = nullptr;
+  int C = 0, d = 0, L = 1, n_burn = 0, n_samples = 0, n_adapt = 0, done = 0;
+  float target = 0.75f;
+  uint64_t seed = 0;
+  char* base = nullptr;
+  HmcArgs a{};
+  FitBuffers fb;  // holds the priors (and unused fit arrays)
+};
+
+static int hmc_launch1(void (*k)(HmcArgs), const HmcArgs& a, int n, int threads, hipStream_t st) {
+  hipLaunchKernelGGL(k, dim3((n + threads - 1) / threads), dim3(threads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
+}
+
+static int hmc_move(const HmcArgs& a, float scale, int drift, hipStream_t st) {
+  hipLaunchKernelGGL(hmc_move_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a, scale, drift);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
+}
+
+// Lower Cholesky factor of the symmetric matrix s [d][d] (row-major, double); false unless
+// positive definite.
+static bool cholesky(std::vector<double>& s, int d) {
+  for (int j = 0; j < d; ++j) {
+    double diag = s[j * d + j];
+    for (int k = 0; k < j; ++k) diag -= s[j * d + k] * s[j * d + k];
+    if (!(diag > 0.0) || !std::isfinite(diag)) return false;
+    const double ljj = std::sqrt(diag);
+    s[j * d + j] = ljj;
+    for (int i = j + 1; i < d; ++i) {
+      double v = s[i * d + j];
+      for (int k = 0; k < j; ++k) v -= s[i * d + k] * s[j * d + k];
+      s[i * d + j] = v / ljj;
+    }
+    for (int k = j + 1; k < d; ++k) s[j * d + k] = 0.0;
+  }
+  return true;
+}
+
+// Transposed inverse of the lower-triangular l [d][d] (upper triangular result).
+static std::vector<double> inverse_transpose_lower(const std::vector<double>& l, int d) {
+  std::vector<double> inv(size_t(d) * d, 0.0);  // inv = l^-1, lower triangular
+  for (int c = 0; c < d; ++c) {  // solve l x = e_c by forward substitution
+    for (int i = c; i < d; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= l[i * d + k] * inv[k * d + c];
+      inv[i * d + c] = v / l[i * d + i];
+    }
+  }
+  std::vector<double> t(size_t(d) * d);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) t[i * d + j] = inv[j * d + i];
+  return t;
+}
+
+static int hmc_gradient(gl_hmc* h, hipStream_t st) {
+  gl_model* m = h->model;
+  const ModelCfg& c = m->sys.cfg;
+  const int tiles = choose_tiles(h->C, c.H * c.W);
+  // Another call on the model may have regrown its workspace: reserve and re-read.
+  int rc = workspace_reserve(m->ws, h->C, tiles, c.H * c.W, c.d, true);
+  if (rc) return rc;
+  Group g;
+  std::memset(&g, 0, sizeof(g));
+  g.nsys = 1;
+  g.sys[0] = make_sys(m->sys, m->ws, h->C, tiles);
+  g.sys[0].theta = nullptr;
+  g.sys[0].z = h->a.z32;
+  g.sys[0].prior = h->fb.prior;
+  g.sys[0].theta_out = m->ws.theta;
+  g.sys[0].logl = m->ws.logl;
+  g.sys[0].grad = m->ws.grad;
+  h->a.logl = m->ws.logl;
+  h->a.grad = m->ws.grad;
+  h->a.theta = m->ws.theta;
+  rc = run_group(g, subpix_key(c), c.K, 2, st);
+  if (rc) return rc;
+  return hmc_launch1(hmc_lp_grad_kernel, h->a, h->C, 64, st);
+}
+
+static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
+  HmcArgs& a = h->a;
+  int rc = GL_OK;
+  hipLaunchKernelGGL(hmc_draw_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a);
+  if (hipGetLastError() != hipSuccess) rc = set_error(GL_E_DEVICE, "draw launch failed");
+  if (!rc) rc = hmc_move(a, 0.5f, 1, st);
+  for (int l = 0; !rc && l < h->L; ++l) {
+    rc = hmc_gradient(h, st);
+    if (!rc) rc = hmc_move(a, l + 1 < h->L ? 1.0f : 0.5f, l + 1 < h->L, st);
+  }
+  if (!rc) {
+    hipLaunchKernelGGL(hmc_finish_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a);
+    if (hipGetLastError() != hipSuccess) rc = set_error(GL_E_DEVICE, "finish launch failed");
+  }
+  if (!rc) rc = hmc_launch1(hmc_adapt_kernel, a, 1, 64, st);
+  if (!rc) h->done++;
+  return rc;
+}
+
+extern "C" {
+
+int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** out,
+                  void* stream) {
+  clear_error();
+  if (!out) return set_error(GL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!m || !o) return set_error(GL_E_INVALID, "NULL argument");
+  if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
+  if (o->chains < 1 || o->n_leapfrog < 1 || o->n_burn < 0 || o->n_samples < 0)
+    return set_error(GL_E_INVALID, "need chains >= 1, n_leapfrog >= 1, n_burn, n_samples >= 0");
+  if (!(o->step_size > 0.f) || !std::isfinite(o->step_size))
+    return set_error(GL_E_INVALID, "step_size must be > 0");
+  if (!(o->target_accept > 0.f && o->target_accept < 1.f))
+    return set_error(GL_E_INVALID, "target_accept must be in (0, 1)");
+  if (!(o->adapt_frac >= 0.f && o->adapt_frac <= 1.f))
+    return set_error(GL_E_INVALID, "adapt_frac must be in [0, 1]");
+  const ModelCfg& c = m->sys.cfg;
+  const int C = o->chains, d = c.d;
+  gl_fit_opts fo;
+  std::memset(&fo, 0, sizeof(fo));
+  fo.P = C;
+  fo.K = 1;
+  fo.priors = o->priors;
+  std::vector<Prior> pri;
+  int rc = validate_fit_opts(&fo, d, pri);
+  if (rc) return rc;
+  // M^-1 = S = chol chol^T (identity, diagonal or dense), factored in double on the host.
+  std::vector<double> S(size_t(d) * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double v = 1.0;
+    if (o->inv_mass && !o->inv_mass_dense) v = o->inv_mass[j];
+    S[size_t(j) * d + j] = v;
+  }
+  if (o->inv_mass && o->inv_mass_dense) {
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        const double v = o->inv_mass[i * d + j], vt = o->inv_mass[j * d + i];
+        if (!std::isfinite(v) || std::fabs(v - vt) > 1e-6 * (std::fabs(v) + std::fabs(vt)))
+          return set_error(GL_E_INVALID, "inv_mass must be finite and symmetric");
+        S[size_t(i) * d + j] = v;
+      }
+  }
+  if (!cholesky(S, d)) return set_error(GL_E_INVALID, "inv_mass must be positive definite");
+  const std::vector<double> SIT = inverse_transpose_lower(S, d);
+  std::vector<float> chol(S.begin(), S.end()), chol_it(SIT.begin(), SIT.end());
+  if (z0 && (rc = check_device_ptr(z0, "z0"))) return rc;
+  gl_hmc* h = new (std::nothrow) gl_hmc();
+  if (!h) return set_error(GL_E_NOMEM, "host allocation failed");
+  h->model = m;
+  h->C = C;
+  h->d = d;
+  h->L = o->n_leapfrog;
+  h->n_burn = o->n_burn;
+  h->n_samples = o->n_samples;
+  h->n_adapt = int(std::floor(double(o->adapt_frac) * o->n_burn));
+  h->target = o->target_accept;
+  hipStream_t st = (hipStream_t)stream;
+  rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true);
+  if (!rc) rc = fit_buffers_alloc(h->fb, C, d, pri.data());
+  const size_t cd = size_t(C) * d;
+  const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 2 * C + 8) +
+                       sizeof(double) * (2 * cd + 3 * C + 8) +
+                       sizeof(float) * size_t(o->n_samples) * cd + 256 * 24;
+  if (!rc && hipMalloc(&h->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
+  if (rc) {
+    fit_buffers_free(h->fb);
+    delete h;
+    return rc;
+  }
+  char* q = h->base;
+  auto take = [&](size_t b) {
+    char* r = q;
+    q += (b + 255) & ~size_t(255);
+    return r;
+  };
+  HmcArgs& a = h->a;
+  a.C = C;
+  a.d = d;
+  a.n_burn = o->n_burn;
+  a.n_adapt = h->n_adapt;
+  a.target = o->target_accept;
+  a.prior = h->fb.prior;
+  a.z = reinterpret_cast<double*>(take(sizeof(double) * cd));
+  a.z32 = reinterpret_cast<float*>(take(sizeof(float) * cd));
+  a.p = reinterpret_cast<float*>(take(sizeof(float) * cd));
+  a.g = reinterpret_cast<float*>(take(sizeof(float) * cd));
+  a.zs = reinterpret_cast<double*>(take(sizeof(double) * cd));
+  a.gs = reinterpret_cast<float*>(take(sizeof(float) * cd));
+  float* chol_d = reinterpret_cast<float*>(take(sizeof(float) * d * d));
+  float* chol_it_d = reinterpret_cast<float*>(take(sizeof(float) * d * d));
+  a.chol = chol_d;
+  a.chol_it = chol_it_d;
+  a.traj = reinterpret_cast<int*>(take(sizeof(int) * 4));
+  a.accept = reinterpret_cast<float*>(take(sizeof(float) * C));
+  a.eps = reinterpret_cast<float*>(take(sizeof(float) * 4));
+  a.bad = reinterpret_cast<int*>(take(sizeof(int) * C));
+  a.lp = reinterpret_cast<double*>(take(sizeof(double) * C));
+  a.lps = reinterpret_cast<double*>(take(sizeof(double) * C));
+  a.k0 = reinterpret_cast<double*>(take(sizeof(double) * C));
+  a.da = reinterpret_cast<double*>(take(sizeof(double) * 4));
+  a.stats = reinterpret_cast<double*>(take(sizeof(double) * 4));
+  a.samples = o->n_samples ? reinterpret_cast<float*>(take(sizeof(float) * size_t(o->n_samples) * cd))
+                           : nullptr;
+  a.logl = m->ws.logl;
+  a.grad = m->ws.grad;
+  a.theta = m->ws.theta;
+  a.seed_lo = uint32_t(o->seed);
+  a.seed_hi = uint32_t(o->seed >> 32);
+  const double da0[4] = {std::log(10.0 * o->step_size), 0.0, 0.0, 0.0};
+  const double st0[4] = {0.0, 0.0, 0.0, 0.0};
+  const float eps0 = o->step_size;
+  const int zero = 0;
+  bool ok = hipMemcpy(chol_d, chol.data(), sizeof(float) * d * d, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(chol_it_d, chol_it.data(), sizeof(float) * d * d, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.traj, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.da, da0, sizeof(da0), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.stats, st0, sizeof(st0), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.eps, &eps0, sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && z0) ok = hipMemcpyAsync(a.z, z0, sizeof(double) * cd, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (!ok) rc = set_error(GL_E_DEVICE, "upload failed");
+  if (!rc) rc = hmc_launch1(z0 ? hmc_round_kernel : hmc_start_kernel, a, int(cd), 256, st);
+  if (!rc) rc = hmc_gradient(h, st);
+  if (rc) {
+    (void)hipFree(h->base);
+    fit_buffers_free(h->fb);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return GL_OK;
+}
+
+int gl_hmc_destroy(gl_hmc* h) {
+  clear_error();
+  if (!h) return GL_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(h->base);
+  fit_buffers_free(h->fb);
+  delete h;
+  return GL_OK;
+}
+
+int gl_hmc_run(gl_hmc* h, int n, void* stream) {
+  clear_error();
+  if (!h) return set_error(GL_E_INVALID, "state is NULL");
+  if (n < 0) return set_error(GL_E_INVALID, "n must be >= 0");
+  const int total = h->n_burn + h->n_samples;
+  if (h->done + n > total)
+    return set_error(GL_E_INVALID, "%d trajectories requested, %d left", n, total - h->done);
+  h->a.eps_fixed = 0.f;
+  for (int i = 0; i < n; ++i) {
+    int rc = hmc_trajectory(h, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GL_OK;
+}
+
+int gl_hmc_samples(gl_hmc* h, float* theta, void* stream) {
+  clear_error();
+  if (!h) return set_error(GL_E_INVALID, "state is NULL");
+  if (!h->n_samples) return GL_OK;
+  int rc = check_device_ptr(theta, "theta");
+  if (rc) return rc;
+  GL_HIP(hipMemcpyAsync(theta, h->a.samples, sizeof(float) * size_t(h->n_samples) * h->C * h->d,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return GL_OK;
+}
+
+int gl_hmc_get_info(gl_hmc* h, gl_hmc_info* out, void* stream) {
+  clear_error();
+  if (!h || !out) return set_error(GL_E_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  float eps = 0.f;
+  double stats[2] = {0.0, 0.0};
+  GL_HIP(hipMemcpyAsync(&eps, h->a.eps, sizeof(float), hipMemcpyDeviceToHost, st));
+  GL_HIP(hipMemcpyAsync(stats, h->a.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+  GL_HIP(hipStreamSynchronize(st));
+  out->step_size = eps;
+  out->accept_mean = stats[1] > 0 ? stats[0] / stats[1] : 0.0;
+  out->trajectories = h->done;
+  return GL_OK;
+}
+
+int gl_hmc_leapfrog(gl_hmc* h, const double* z, const float* p, int L, float eps,
+                    double* z_out, float* p_out, double* logpost_out, void* stream) {
+  clear_error();
+  if (!h) return set_error(GL_E_INVALID, "state is NULL");
+  if (L < 1 || !(eps > 0.f)) return set_error(GL_E_INVALID, "need L >= 1 and eps > 0");
+  int rc;
+  if ((rc = check_device_ptr(z, "z")) || (rc = check_device_ptr(p, "p")) ||
+      (rc = check_device_ptr(z_out, "z_out")) || (rc = check_device_ptr(p_out, "p_out")) ||
+      (rc = check_device_ptr(logpost_out, "logpost_out")))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t b = sizeof(float) * size_t(h->C) * h->d;
+  HmcArgs& a = h->a;
+  GL_HIP(hipMemcpyAsync(a.z, z, 2 * b, hipMemcpyDeviceToDevice, st));
+  GL_HIP(hipMemcpyAsync(a.p, p, b, hipMemcpyDeviceToDevice, st));
+  a.eps_fixed = eps;
+  rc = hmc_launch1(hmc_round_kernel, a, h->C * h->d, 256, st);
+  if (!rc) rc = hmc_gradient(h, st);
+  if (!rc) rc = hmc_move(a, 0.5f, 1, st);
+  for (int l = 0; !rc && l < L; ++l) {
+    rc = hmc_gradient(h, st);
+    if (!rc) rc = hmc_move(a, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);
+  }
+  a.eps_fixed = 0.f;
+  if (rc) return rc;
+  GL_HIP(hipMemcpyAsync(z_out, a.z, 2 * b, hipMemcpyDeviceToDevice, st));
+  GL_HIP(hipMemcpyAsync(p_out, a.p, b, hipMemcpyDeviceToDevice, st));
+  GL_HIP(hipMemcpyAsync(logpost_out, a.lp, sizeof(double) * h->C, hipMemcpyDeviceToDevice, st));
+  return GL_OK;
+}
+
+}  // extern "C"

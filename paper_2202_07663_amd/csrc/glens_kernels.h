@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "glens_device.h"
+#include "glens_fit_device.h"
 
 namespace glens {
 
@@ -23,14 +24,6 @@ constexpr int kSubThreads = 256;
 constexpr int kConvThreads = 256;
 constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
 constexpr int kConvMaxStrips = 8;  // strips per lane: (H/8 rounded up) * W <= 8 * 256
-
-// --- bijectors (Sec. 2.2): exp for log-normal priors, sigmoid onto (lo, hi) for truncated
-// normal and uniform priors, identity for normal priors ---
-__device__ __forceinline__ float bijector_fwd(const Prior& pr, float z) {
-  if (pr.family == 1) return expf(z);
-  if (pr.family == 2 || pr.family == 3) return pr.lo + (pr.hi - pr.lo) / (1.0f + expf(-z));
-  return z;
-}
 
 // ------------------------------------------------------------------------------------------
 // prologue: one lane per particle

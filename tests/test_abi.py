@@ -80,3 +80,18 @@ def test_nonfinite_psf_rejected(lib):
     h = ctypes.c_void_p()
     assert lib.gl_model_create(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"psf" in lib.gl_last_error()
+
+
+def test_hmc_entry_points_reject_null_handles(lib):
+    from paper_2202_07663_amd import _lib
+    h = ctypes.c_void_p()
+    o = _lib.HmcOpts(chains=4, n_leapfrog=2, n_burn=1, n_samples=1, step_size=0.1,
+                     target_accept=0.75, adapt_frac=0.8)
+    assert lib.gl_hmc_create(None, ctypes.byref(o), None, ctypes.byref(h), None) == -1
+    assert lib.gl_last_error()
+    assert lib.gl_hmc_create(None, ctypes.byref(o), None, None, None) == -1
+    assert lib.gl_hmc_run(None, 1, None) == -1
+    assert lib.gl_hmc_samples(None, None, None) == -1
+    assert lib.gl_hmc_get_info(None, None, None) == -1
+    assert lib.gl_hmc_leapfrog(None, None, None, 1, 0.1, None, None, None, None) == -1
+    assert lib.gl_hmc_destroy(None) == 0

@@ -1,0 +1,193 @@
+"""GPU tests of the HMC sampler (Sec. 2.5) through the C ABI: leapfrog parity with the FP64
+oracle (oracle/hmc.py), reversibility, step-size adaptation, and the sampled distribution
+against the Laplace approximation of a high signal-to-noise posterior."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fit as ofit
+from oracle import hmc as ohmc
+import synth
+from paper_2202_07663_amd import diagnostics as dg
+from tests.helpers import load_workload, oracle_model
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_2202_07663_amd as g
+    return g
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _laplace_sie40():
+    spec = synth.spec_c1()
+    obs, truth = load_workload(spec.name)
+    priors = synth.fit_priors(spec)
+    fg = ohmc.lens_objective(oracle_model(spec), obs, priors)
+    z_true = ofit.bijector_inverse(truth[None, :].astype(np.float64), priors)[0]
+    z_mode, hess = ohmc.newton_mode(fg, z_true)
+    return spec, obs, priors, fg, z_mode, np.linalg.inv(hess)
+
+
+def _near_truth_epl36():
+    """A small EPL + lens light + shapelet system; M^-1 = 1 / diag(Hessian) at the truth."""
+    spec = synth.Spec("hmcepl", 36, 36, 2, epl=True, lens_light=True, nmax=3,
+                      psf=synth.moffat_psf(9, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
+    truth = synth.draw_truth(spec, 31)
+    om = oracle_model(spec)
+    obs = synth.add_noise(oracle.simulate(om, truth.astype(np.float64))[0], 31, 0.1, 1000.0)
+    priors = synth.fit_priors(spec)
+    fg = ohmc.lens_objective(om, obs, priors)
+    z = ofit.bijector_inverse(truth[None, :].astype(np.float64), priors)[0]
+    return spec, obs, priors, fg, z, 1.0 / np.abs(np.diag(ohmc.hessian_fd(fg, z)))
+
+
+@pytest.fixture(scope="module")
+def sie40():
+    return _laplace_sie40()
+
+
+def _whiten(inv_mass):
+    im = np.asarray(inv_mass, np.float64)
+    return np.sqrt(np.diag(im) if im.ndim == 2 else im)
+
+
+def _white(inv_mass):
+    """Maps taking position and momentum differences to units where M^-1 = I:
+    dz -> C^-1 dz, dp -> C^T dp for M^-1 = C C^T."""
+    im = np.asarray(inv_mass, np.float64)
+    C = np.linalg.cholesky(im) if im.ndim == 2 else np.diag(np.sqrt(im))
+    Ci = np.linalg.inv(C)
+    return (lambda dz: dz @ Ci.T), (lambda dp: dp @ C)
+
+
+@pytest.mark.parametrize("case", ["sie40_dense", "epl36_diag"])
+def test_leapfrog_parity(G, sie40, case):
+    """L leapfrog steps on the GPU (FP32 positions and momenta, the library's gradient) from
+    the same (z, p) as the oracle's FP64 integration. Compared in units of the posterior
+    width: |dz| / w and |dp| w within 2e-3 (1 + the distance travelled), the end log
+    posterior within the log-likelihood bar (relative 1e-4)."""
+    if case == "sie40_dense":
+        spec, obs, priors, fg, z_c, im = sie40
+        eps, L = 0.3, 5
+    else:
+        spec, obs, priors, fg, z_c, im = _near_truth_epl36()
+        eps, L = 0.05, 6
+    w = _whiten(im)
+    C = 16
+    rng = np.random.default_rng(7)
+    z0 = z_c + 0.7 * rng.normal(size=(C, z_c.size)) * w
+    p0 = (rng.normal(size=z0.shape) / w).astype(np.float32)
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, L, 0, 0, priors, inv_mass=im, z0=torch.from_numpy(z0).cuda())
+    zg, pg, lpg = (t.cpu().numpy().astype(np.float64)
+                   for t in h.leapfrog(torch.from_numpy(z0).cuda(), torch.from_numpy(p0).cuda(),
+                                       L, eps))
+    zr, pr, _, fr = ohmc.leapfrog_fn(fg, z0, p0.astype(np.float64), eps, L,
+                                     np.asarray(im, np.float64))
+    assert np.all(np.isfinite(zr)) and np.all(np.isfinite(fr))
+    wz, wp = _white(im)
+    travel = max(np.abs(wz(zr - z0)).max(), np.abs(wp(pr - p0)).max())
+    ez, ep = np.abs(wz(zg - zr)).max(), np.abs(wp(pg - pr)).max()
+    elp = np.abs(lpg + fr).max() / np.abs(fr).max()
+    _say(case, "travel", travel, "max |dz|", ez, "max |dp|", ep, "lp rel", elp)
+    # per-parameter detail, and the gradient of log p~ at the start against the oracle
+    _say("dz/w by param", np.round(np.abs((zg - zr) / w).max(axis=0), 4))
+    _say("dp w by param", np.round(np.abs((pg - pr) * w).max(axis=0), 4))
+    th0 = torch.from_numpy(ofit.bijector(z0.astype(np.float64), priors).astype(np.float32)).cuda()
+    _, gth = model.loglik_grad(th0)
+    _, gth_ref = oracle.loglik_grad(oracle_model(spec), th0.cpu().numpy().astype(np.float64), obs)
+    gw = np.abs((gth.cpu().numpy() - gth_ref)).max(axis=0) / (np.abs(gth_ref).max(axis=0) + 1e-30)
+    _say("grad rel err by param", np.round(gw, 6))
+    assert ez <= 2e-3 * (1 + travel) and ep <= 2e-3 * (1 + travel)
+    assert elp <= 1e-4
+
+
+def test_leapfrog_is_reversible_on_the_gpu(G, sie40):
+    """Integrating back with the momentum negated returns to the start (in units where
+    M^-1 = I), up to the FP32 rounding of momenta and of the likelihood's parameters."""
+    spec, obs, priors, fg, z_c, im = sie40
+    w = _whiten(im)
+    C = 32
+    rng = np.random.default_rng(8)
+    z0 = torch.from_numpy(z_c + rng.normal(size=(C, z_c.size)) * w).cuda()
+    p0 = torch.from_numpy((rng.normal(size=(C, z_c.size)) / w).astype(np.float32)).cuda()
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 5, 0, 0, priors, inv_mass=im, z0=z0)
+    z1, p1, _ = h.leapfrog(z0, p0, 8, 0.3)
+    z2, p2, _ = h.leapfrog(z1, -p1, 8, 0.3)
+    wz, wp = _white(im)
+    d = lambda t: t.cpu().numpy().astype(np.float64)
+    moved = np.abs(wz(d(z1) - d(z0))).max()
+    ez = np.abs(wz(d(z2) - d(z0))).max()
+    ep = np.abs(wp(d(p2) + d(p0))).max()
+    _say("moved", moved, "return error z", ez, "p", ep)
+    assert moved > 0.1 and ez < 2e-3 and ep < 2e-3
+
+
+def test_sampler_matches_the_laplace_posterior(G, sie40):
+    """At this signal-to-noise the posterior is close to Gaussian: 64 chains (the paper's
+    L = 5, M^-1 = the posterior covariance, target acceptance 0.75 adapted over 80% of
+    burn-in) reproduce the Laplace mean and widths, with R-hat < 1.05 and the acceptance
+    near its target. The initial step (1.0) is far from the adapted one."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    C, nb, ns = 64, 150, 250
+    rng = np.random.default_rng(9)
+    z0 = z_c + rng.normal(size=(C, z_c.size)) @ np.linalg.cholesky(cov).T
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 5, nb, ns, priors, step_size=1.0, seed=11, inv_mass=cov,
+              z0=torch.from_numpy(z0).cuda())
+    h.run()
+    info = h.info()
+    th = h.samples().cpu().numpy().astype(np.float64)  # [ns, C, d]
+    z = ofit.bijector_inverse(th.reshape(-1, th.shape[-1]), priors).reshape(th.shape)
+    sd = np.sqrt(np.diag(cov))
+    mean_err = np.abs(z.mean(axis=(0, 1)) - z_c) / sd
+    sd_ratio = z.std(axis=(0, 1)) / sd
+    rhat, ess = dg.split_rhat(z), dg.ess(z)
+    _say("eps", info["step_size"], "accept", info["accept_mean"], "mean err/sd", mean_err.max(),
+         "sd ratio", sd_ratio.min(), sd_ratio.max(), "rhat", rhat.max(), "ess", ess.min())
+    assert info["trajectories"] == nb + ns
+    assert abs(info["accept_mean"] - 0.75) < 0.1
+    assert 0.1 < info["step_size"] < 1.0
+    assert rhat.max() < 1.05 and ess.min() > 500
+    assert mean_err.max() < 0.15
+    assert np.all(np.abs(sd_ratio - 1) < 0.12)
+
+
+def test_sampler_is_deterministic_and_seeded(G, sie40):
+    spec, obs, priors, fg, z_c, cov = sie40
+    z0 = torch.from_numpy(np.tile(z_c, (8, 1))).cuda()
+    model = G.Model.from_spec(spec, obs)
+    runs = []
+    for seed in (3, 3, 4):
+        h = G.HMC(model, 8, 5, 10, 10, priors, step_size=0.3, seed=seed, inv_mass=cov, z0=z0)
+        h.run(12)
+        h.run(8)
+        runs.append(h.samples().cpu().numpy())
+        h.close()
+    np.testing.assert_array_equal(runs[0], runs[1])
+    assert not np.array_equal(runs[0], runs[2])
+
+
+def test_sampler_from_prior_starts_and_bad_options(G, sie40):
+    """Chains drawn from the prior (far from the posterior, where log L may overflow) run
+    without failing and report finite samples; invalid options are refused."""
+    spec, obs, priors, _, _, cov = sie40
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, 16, 3, 2, 2, priors, step_size=1e-3, seed=1)
+    h.run()
+    assert np.all(np.isfinite(h.samples().cpu().numpy()))
+    with pytest.raises(G.GlError):
+        h.run(1)  # nothing left
+    bad = -np.eye(spec.d)
+    with pytest.raises(G.GlError):
+        G.HMC(model, 4, 3, 1, 1, priors, inv_mass=bad)
+    with pytest.raises(G.GlError):
+        G.HMC(model, 4, 3, 1, 1, priors, target_accept=1.5)
