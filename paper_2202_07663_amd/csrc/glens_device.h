@@ -93,9 +93,12 @@ GL_HD void decode_light(const float* th, LightC& L) {
   L.j22 = float(j22);
 }
 
-// Decode one parameter vector (layout of gl.h) into the per-particle constants.
-GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light, int nmax,
-                           PConst& c) {
+// Number of parameters of the mass model (lens mass + external shear) in the gl.h layout.
+GL_HD int mass_param_count(int mass, int shear) { return 5 + (mass == 1) + 2 * shear; }
+
+// Mass constants of one parameter vector (layout of gl.h): everything but the series
+// coefficients, whose term counts it sets.
+GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   int p = 0;
   const double theta_e = th[p++];
   const double t = (mass == 1) ? double(th[p++]) - 1.0 : 1.0;
@@ -140,18 +143,6 @@ GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light,
   }
   c.nterms = nt;
   c.nterms_d = ntd;
-  double cn = 1.0, dsum = 0.0;
-  for (int n = 0; n < kMaxTerms; ++n) {
-    if (n > 0) {
-      const double a = 2.0 * n - 2.0 + t, b = 2.0 * n + 2.0 - t;
-      cn *= a / b;
-      dsum += 1.0 / a + 1.0 / b;
-    }
-    c.c[n] = n < nt ? cn : 0.0;
-    c.dc[n] = n < ntd ? float(cn * dsum) : 0.f;
-    if (n > 0) c.nc[n - 1] = n < ntd ? float(n * cn) : 0.f;
-  }
-  c.nc[kMaxTerms - 1] = 0.f;
   // SIE closed form: s = sqrt(conj(eps)), S_1(X) = atan(s u) / (s u), u = w / |w|
   c.sie_closed = (mass == 0 && eabs >= kSieClosedMin) ? 1 : 0;
   if (c.sie_closed) {
@@ -161,6 +152,29 @@ GL_HD void decode_particle(const float* th, int mass, int shear, int lens_light,
   } else {
     c.sr = c.si = 0.0;
   }
+}
+
+// Series ratio c_n / c_{n-1} = (2n - 2 + t) / (2n + 2 - t) and the increment of
+// d log c_n / dt, 1 / (2n - 2 + t) + 1 / (2n + 2 - t), for n >= 1.
+GL_HD void series_step(int n, double t, double& ratio, double& dlog) {
+  const double a = 2.0 * n - 2.0 + t, b = 2.0 * n + 2.0 - t;
+  ratio = a / b;
+  dlog = 1.0 / a + 1.0 / b;
+}
+
+// Stores term n of the value series (c_n), of the derivative series n c_n (at n - 1) and
+// of dc_n / dt = c_n sum_k dlog_k, given the running product and sum.
+GL_HD void series_store(PConst& c, int n, double cn, double dsum) {
+  c.c[n] = n < c.nterms ? cn : 0.0;
+  c.dc[n] = n < c.nterms_d ? float(cn * dsum) : 0.f;
+  if (n > 0) c.nc[n - 1] = n < c.nterms_d ? float(n * cn) : 0.f;
+  if (n == kMaxTerms - 1) c.nc[kMaxTerms - 1] = 0.f;
+}
+
+// Light constants (lens light, source Sersic, shapelet coefficients) of one vector.
+GL_HD void decode_lights(const float* th, int mass, int shear, int lens_light, int nmax,
+                         PConst& c) {
+  int p = mass_param_count(mass, shear);
   c.lxs = c.lys = 0.0;
   if (lens_light) {
     decode_light(th + p, c.lens);

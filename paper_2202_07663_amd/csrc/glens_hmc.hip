@@ -75,29 +75,72 @@ __device__ __forceinline__ void chol_t_times(const HmcArgs& a, const float* x, f
   }
 }
 
-// log p~(z | I) and its gradient from the pipeline outputs (one lane per chain).
-__global__ void __launch_bounds__(64) hmc_lp_grad_kernel(HmcArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.C) return;
-  const double ll = a.logl[c];
-  double lp = ll;
-  for (int j = 0; j < a.d; ++j) {
-    const size_t i = size_t(c) * a.d + j;
-    float dlp, dth;
-    lp += log_prior_z(a.prior[j], a.z32[i], a.theta[i], dlp, dth);
-    a.g[i] = a.grad[i] * dth + dlp;
+// p += scale eps g (scale 0: no kick); then, if drift, z += eps chol (chol^T p). p is
+// mirrored in s_p. One block per chain; the caller has synchronised the block.
+__device__ __forceinline__ void kick_drift(const HmcArgs& a, const float* s_g, float scale,
+                                           int drift, float* s_p, float* s_v) {
+  const int c = blockIdx.x;
+  const float eps = step_size(a);
+  const size_t row = size_t(c) * a.d;
+  if (scale != 0.f) {
+    for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+      const float pn = a.p[row + j] + scale * eps * s_g[j];
+      a.p[row + j] = pn;
+      s_p[j] = pn;
+    }
   }
-  if (!isfinite(lp)) {
-    lp = -INFINITY;
-    a.bad[c] = 1;
-    for (int j = 0; j < a.d; ++j) a.g[size_t(c) * a.d + j] = 0.f;
+  if (!drift) return;
+  __syncthreads();
+  chol_t_times(a, s_p, s_v);
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    float s = 0.f;
+    for (int i = 0; i <= j; ++i) s += a.chol[j * a.d + i] * s_v[i];
+    const double zn = a.z[row + j] + double(eps) * s;
+    a.z[row + j] = zn;
+    a.z32[row + j] = float(zn);
   }
-  a.lp[c] = lp;
 }
 
-// New momentum p = chol^-T n, saved trajectory start and kinetic energy |n|^2 / 2.
-__global__ void __launch_bounds__(kHmcThreads) hmc_draw_kernel(HmcArgs a) {
-  __shared__ float s_n[kMaxParams];
+// log p~(z | I) and its gradient from the pipeline outputs (terms summed in parameter
+// order by lane 0), then the kick and drift of the leapfrog step.
+__global__ void __launch_bounds__(kHmcThreads) hmc_grad_move_kernel(HmcArgs a, float scale,
+                                                                    int drift) {
+  __shared__ double s_t[kMaxParams];
+  __shared__ float s_g[kMaxParams], s_p[kMaxParams], s_v[kMaxParams];
+  __shared__ int s_bad;
+  const int c = blockIdx.x;
+  const size_t row = size_t(c) * a.d;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    float dlp, dth;
+    s_t[j] = log_prior_z(a.prior[j], a.z32[row + j], a.theta[row + j], dlp, dth);
+    s_g[j] = a.grad[row + j] * dth + dlp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lp = a.logl[c];
+    for (int j = 0; j < a.d; ++j) lp += s_t[j];
+    const int bad = !isfinite(lp);
+    if (bad) {
+      lp = -INFINITY;
+      a.bad[c] = 1;
+    }
+    a.lp[c] = lp;
+    s_bad = bad;
+  }
+  __syncthreads();
+  const int bad = s_bad;
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    if (bad) s_g[j] = 0.f;
+    a.g[row + j] = s_g[j];
+  }
+  kick_drift(a, s_g, scale, drift, s_p, s_v);
+}
+
+// New momentum p = chol^-T n, saved trajectory start and kinetic energy |n|^2 / 2, then the
+// first half kick and drift.
+__global__ void __launch_bounds__(kHmcThreads) hmc_begin_kernel(HmcArgs a) {
+  __shared__ float s_n[kMaxParams], s_g[kMaxParams], s_p[kMaxParams], s_v[kMaxParams];
   const int c = blockIdx.x;
   const int traj = *a.traj;
   const size_t row = size_t(c) * a.d;
@@ -107,7 +150,7 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_draw_kernel(HmcArgs a) {
     const double u1 = u01(w[0], w[1]), u2 = u01(w[2], w[3]);
     s_n[j] = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
     a.zs[row + j] = a.z[row + j];
-    a.gs[row + j] = a.g[row + j];
+    s_g[j] = a.gs[row + j] = a.g[row + j];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < a.d; i += kHmcThreads) {
@@ -122,30 +165,8 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_draw_kernel(HmcArgs a) {
     a.lps[c] = a.lp[c];
     a.bad[c] = 0;
   }
-}
-
-// p += scale eps g; then, if drift, z += eps chol (chol^T p).
-__global__ void __launch_bounds__(kHmcThreads) hmc_move_kernel(HmcArgs a, float scale, int drift) {
-  __shared__ float s_p[kMaxParams], s_v[kMaxParams];
-  const int c = blockIdx.x;
-  const float eps = step_size(a);
-  const size_t row = size_t(c) * a.d;
-  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
-    const float pn = a.p[row + j] + scale * eps * a.g[row + j];
-    a.p[row + j] = pn;
-    s_p[j] = pn;
-  }
-  if (!drift) return;
   __syncthreads();
-  chol_t_times(a, s_p, s_v);
-  __syncthreads();
-  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
-    float s = 0.f;
-    for (int i = 0; i <= j; ++i) s += a.chol[j * a.d + i] * s_v[i];
-    const double zn = a.z[row + j] + double(eps) * s;
-    a.z[row + j] = zn;
-    a.z32[row + j] = float(zn);
-  }
+  kick_drift(a, s_g, 0.5f, 1, s_p, s_v);
 }
 
 // Metropolis accept / reject and the sample record.
@@ -258,8 +279,9 @@ static int hmc_launch1(void (*k)(HmcArgs), const HmcArgs& a, int n, int threads,
   return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
 }
 
-static int hmc_move(const HmcArgs& a, float scale, int drift, hipStream_t st) {
-  hipLaunchKernelGGL(hmc_move_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a, scale, drift);
+static int hmc_chain_launch(void (*k)(HmcArgs, float, int), const HmcArgs& a, float scale,
+                            int drift, hipStream_t st) {
+  hipLaunchKernelGGL(k, dim3(a.C), dim3(kHmcThreads), 0, st, a, scale, drift);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
 }
@@ -299,7 +321,9 @@ static std::vector<double> inverse_transpose_lower(const std::vector<double>& l,
   return t;
 }
 
-static int hmc_gradient(gl_hmc* h, hipStream_t st) {
+// log p~(z | I) and its gradient at the chains' current positions, then a leapfrog kick
+// of scale eps (scale 0: none) and, if drift, a drift.
+static int hmc_gradient(gl_hmc* h, float scale, int drift, hipStream_t st) {
   gl_model* m = h->model;
   const ModelCfg& c = m->sys.cfg;
   const int tiles = choose_tiles(h->C, c.H * c.W);
@@ -321,23 +345,15 @@ static int hmc_gradient(gl_hmc* h, hipStream_t st) {
   h->a.theta = m->ws.theta;
   rc = run_group(g, subpix_key(c), c.K, 2, st);
   if (rc) return rc;
-  return hmc_launch1(hmc_lp_grad_kernel, h->a, h->C, 64, st);
+  return hmc_chain_launch(hmc_grad_move_kernel, h->a, scale, drift, st);
 }
 
 static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
   HmcArgs& a = h->a;
-  int rc = GL_OK;
-  hipLaunchKernelGGL(hmc_draw_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a);
-  if (hipGetLastError() != hipSuccess) rc = set_error(GL_E_DEVICE, "draw launch failed");
-  if (!rc) rc = hmc_move(a, 0.5f, 1, st);
-  for (int l = 0; !rc && l < h->L; ++l) {
-    rc = hmc_gradient(h, st);
-    if (!rc) rc = hmc_move(a, l + 1 < h->L ? 1.0f : 0.5f, l + 1 < h->L, st);
-  }
-  if (!rc) {
-    hipLaunchKernelGGL(hmc_finish_kernel, dim3(a.C), dim3(kHmcThreads), 0, st, a);
-    if (hipGetLastError() != hipSuccess) rc = set_error(GL_E_DEVICE, "finish launch failed");
-  }
+  int rc = hmc_launch1(hmc_begin_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
+  for (int l = 0; !rc && l < h->L; ++l)
+    rc = hmc_gradient(h, l + 1 < h->L ? 1.0f : 0.5f, l + 1 < h->L, st);
+  if (!rc) rc = hmc_launch1(hmc_finish_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_adapt_kernel, a, 1, 64, st);
   if (!rc) h->done++;
   return rc;
@@ -465,7 +481,7 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   if (ok && z0) ok = hipMemcpyAsync(a.z, z0, sizeof(double) * cd, hipMemcpyDeviceToDevice, st) == hipSuccess;
   if (!ok) rc = set_error(GL_E_DEVICE, "upload failed");
   if (!rc) rc = hmc_launch1(z0 ? hmc_round_kernel : hmc_start_kernel, a, int(cd), 256, st);
-  if (!rc) rc = hmc_gradient(h, st);
+  if (!rc) rc = hmc_gradient(h, 0.f, 0, st);
   if (rc) {
     (void)hipFree(h->base);
     fit_buffers_free(h->fb);
@@ -544,12 +560,8 @@ int gl_hmc_leapfrog(gl_hmc* h, const double* z, const float* p, int L, float eps
   GL_HIP(hipMemcpyAsync(a.p, p, b, hipMemcpyDeviceToDevice, st));
   a.eps_fixed = eps;
   rc = hmc_launch1(hmc_round_kernel, a, h->C * h->d, 256, st);
-  if (!rc) rc = hmc_gradient(h, st);
-  if (!rc) rc = hmc_move(a, 0.5f, 1, st);
-  for (int l = 0; !rc && l < L; ++l) {
-    rc = hmc_gradient(h, st);
-    if (!rc) rc = hmc_move(a, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);
-  }
+  if (!rc) rc = hmc_gradient(h, 0.5f, 1, st);
+  for (int l = 0; !rc && l < L; ++l) rc = hmc_gradient(h, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);
   a.eps_fixed = 0.f;
   if (rc) return rc;
   GL_HIP(hipMemcpyAsync(z_out, a.z, 2 * b, hipMemcpyDeviceToDevice, st));

@@ -72,7 +72,7 @@ int launch_finalize(const Group& g, hipStream_t st);
 size_t conv_lds_bytes(int H, int W, int K, int mode);
 
 // Block counts of one system per stage.
-inline int blocks_prologue(const SysDesc& s) { return (s.P + 63) / 64; }
+inline int blocks_prologue(const SysDesc& s) { return s.P; }  // prologue, finalize
 inline int blocks_subpix(const SysDesc& s) { return s.P * s.tiles; }
 inline int blocks_conv(const SysDesc& s) { return s.P; }
 

@@ -26,26 +26,47 @@ constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
 constexpr int kConvMaxStrips = 8;  // strips per lane: (H/8 rounded up) * W <= 8 * 256
 
 // ------------------------------------------------------------------------------------------
-// prologue: one lane per particle
+// prologue: one 64-lane block per particle. Lane 0 decodes the mass, lane 1 the lights
+// while the lanes compute the series ratios in parallel; lane 0 then forms the running
+// product (in the same order as a serial loop) and the lanes store the coefficients.
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
+  static_assert(kMaxTerms <= 64, "one lane per series term");
+  __shared__ float th[kMaxParams];
+  __shared__ double s_ratio[kMaxTerms], s_dlog[kMaxTerms], s_cn[kMaxTerms], s_ds[kMaxTerms];
   const int si = find_sys(g, blockIdx.x);
   const SysDesc& s = g.sys[si];
-  const int p = (blockIdx.x - g.block0[si]) * blockDim.x + threadIdx.x;
-  if (p >= s.P) return;
-  float th[kMaxParams];
-  const int d = s.d;
-  if (s.z) {
-    for (int j = 0; j < d; ++j) {
-      th[j] = bijector_fwd(s.prior[j], s.z[(size_t)p * d + j]);
-      s.theta_out[(size_t)p * d + j] = th[j];
+  const int p = blockIdx.x - g.block0[si];
+  const int d = s.d, lane = threadIdx.x;
+  for (int j = lane; j < d; j += blockDim.x) {
+    const size_t i = (size_t)p * d + j;
+    if (s.z) {
+      th[j] = bijector_fwd(s.prior[j], s.z[i]);
+      s.theta_out[i] = th[j];
+    } else {
+      th[j] = s.theta[i];
     }
-  } else {
-    for (int j = 0; j < d; ++j) th[j] = s.theta[(size_t)p * d + j];
   }
-  PConst c;
-  decode_particle(th, s.mass, s.shear, s.lens_light, s.nmax, c);
-  s.pc[p] = c;
+  __syncthreads();
+  PConst& c = s.pc[p];
+  if (lane == 0) decode_mass(th, s.mass, s.shear, c);
+  if (lane == 1) decode_lights(th, s.mass, s.shear, s.lens_light, s.nmax, c);
+  const double t = (s.mass == 1) ? double(th[1]) - 1.0 : 1.0;
+  if (lane > 0 && lane < kMaxTerms) series_step(lane, t, s_ratio[lane], s_dlog[lane]);
+  __syncthreads();
+  if (lane == 0) {
+    double cn = 1.0, dsum = 0.0;
+    s_cn[0] = cn;
+    s_ds[0] = dsum;
+    for (int n = 1; n < kMaxTerms; ++n) {
+      cn *= s_ratio[n];
+      dsum += s_dlog[n];
+      s_cn[n] = cn;
+      s_ds[n] = dsum;
+    }
+  }
+  __syncthreads();
+  if (lane < kMaxTerms) series_store(c, lane, s_cn[lane], s_ds[lane]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -247,6 +268,65 @@ constexpr int n_slots() {
   return NMAX < 0 ? A_SHP_BETA : A_SHP_C + (NMAX + 1) * (NMAX + 2) / 2;
 }
 
+constexpr int halved(int n) { return n > 1 ? n / 2 : 1; }
+
+// One step of the transposed butterfly below for a lane holding NV values (all indices
+// compile-time, so the values stay in registers).
+template <int NV>
+__device__ __forceinline__ void wave_sum_step(double* v, int off, int lane) {
+  if constexpr (NV > 1) {
+    const bool up = lane & off;
+#pragma unroll
+    for (int i = 0; i < NV / 2; ++i) {
+      const double send = up ? v[i] : v[i + NV / 2];
+      const double keep = up ? v[i + NV / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, off, 64);
+    }
+  } else {
+    v[0] += __shfl_xor(v[0], off, 64);
+  }
+}
+
+// Wave sums of NS per-lane FP32 values, in FP64, written to out[0 .. NS). A transposed
+// butterfly: with the values padded to N (a power of two), at the step with lane offset o a
+// lane keeps one half of its values, sends the other half to lane ^ o and adds what it
+// receives, so each step halves the values a lane holds. Every sum pairs lanes in the same
+// order as a separate xor butterfly per value would, with about N shuffles instead of
+// 6 NS. The first step shuffles the FP32 values and adds them in FP64.
+template <int NS>
+__device__ __forceinline__ void wave_sums(const float* acc, double* out) {
+  constexpr int N = NS <= 32 ? 32 : (NS <= 64 ? 64 : 128);
+  static_assert(NS <= 128, "too many accumulators");
+  const int lane = threadIdx.x & 63;
+  double v[N / 2];
+  {
+    const bool up = lane & 32;
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      const float lo = i < NS ? acc[i] : 0.f, hi = i + N / 2 < NS ? acc[i + N / 2] : 0.f;
+      const float send = up ? lo : hi;
+      v[i] = double(up ? hi : lo) + double(__shfl_xor(send, 32, 64));
+    }
+  }
+  constexpr int n1 = N / 2, n2 = halved(n1), n3 = halved(n2), n4 = halved(n3), n5 = halved(n4);
+  wave_sum_step<n1>(v, 16, lane);
+  wave_sum_step<n2>(v, 8, lane);
+  wave_sum_step<n3>(v, 4, lane);
+  wave_sum_step<n4>(v, 2, lane);
+  wave_sum_step<n5>(v, 1, lane);
+  // lane l now holds value (l * N / 64) + i for i < N / 64 (N = 32: lanes 2q and 2q + 1
+  // both hold value q)
+  if (N >= 64) {
+#pragma unroll
+    for (int i = 0; i < N / 64; ++i) {
+      const int q = lane * (N / 64) + i;
+      if (q < NS) out[q] = v[i];
+    }
+  } else if ((lane & 1) == 0 && (lane >> 1) < NS) {
+    out[lane >> 1] = v[0];
+  }
+}
+
 template <int MASS, int NMAX>
 __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3)))
 subpix_adj_kernel(Group g) {
@@ -297,14 +377,8 @@ subpix_adj_kernel(Group g) {
     }
   }
   // FP64 sums: across the wave, then across the waves of the block
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    double v = acc[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wave][q] = v;
-  }
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  wave_sums<NS>(acc, red[wave]);
   __syncthreads();
   double* out = s.acc + ((size_t)part * s.tiles + tile) * kNAcc;
   for (int q = threadIdx.x; q < NS; q += blockDim.x) {
@@ -315,28 +389,36 @@ subpix_adj_kernel(Group g) {
 }
 
 // ------------------------------------------------------------------------------------------
-// finalize: one lane per particle
+// finalize: one 64-lane block (a single wave) per particle; lanes sum the tiles' partial
+// accumulators (in tile order), lane 0 maps them to the parameter gradient
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) finalize_kernel(Group g) {
+  __shared__ double a[kNAcc];
   const int si = find_sys(g, blockIdx.x);
   const SysDesc& s = g.sys[si];
-  const int p = (blockIdx.x - g.block0[si]) * blockDim.x + threadIdx.x;
-  if (p >= s.P) return;
-  const PConst& c = s.pc[p];
+  const int p = blockIdx.x - g.block0[si];
   const int ns = s.nmax < 0 ? A_SHP_BETA : A_SHP_C + (s.nmax + 1) * (s.nmax + 2) / 2;
-  double a[kNAcc];
-  for (int q = 0; q < ns; ++q) {
+  const double* acc = s.acc + (size_t)p * s.tiles * kNAcc;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     double v = 0.0;
-    for (int t = 0; t < s.tiles; ++t) v += s.acc[((size_t)p * s.tiles + t) * kNAcc + q];
+#pragma unroll 8
+    for (int t = 0; t < s.tiles; ++t) v += acc[t * kNAcc + q];
     a[q] = v;
   }
-  float gr[kMaxParams];
-  const int j = map_gradient(c, a, s.mass, s.shear, s.lens_light, s.nmax, gr);
-  bool ok = isfinite(s.logl[p]);
-  for (int q = 0; q < j; ++q) ok = ok && isfinite(gr[q]);
-  if (!ok) s.logl[p] = -INFINITY;
+  __syncthreads();
+  // lane 0 maps the sums (to LDS, not to a lane-private array the compiler would spill);
+  // the lanes then check and store the components
+  __shared__ float gr[kMaxParams];
+  __shared__ int s_j;
+  if (threadIdx.x == 0) s_j = map_gradient(s.pc[p], a, s.mass, s.shear, s.lens_light, s.nmax, gr);
+  __syncthreads();
+  const int j = s_j;
+  int bad = 0;
+  for (int q = threadIdx.x; q < j; q += blockDim.x) bad |= !isfinite(gr[q]);
+  const bool ok = isfinite(s.logl[p]) && !__any(bad);
   float* out = s.grad + (size_t)p * s.d;
-  for (int q = 0; q < j; ++q) out[q] = ok ? gr[q] : 0.f;
+  for (int q = threadIdx.x; q < j; q += blockDim.x) out[q] = ok ? gr[q] : 0.f;
+  if (threadIdx.x == 0 && !ok) s.logl[p] = -INFINITY;
 }
 
 }  // namespace glens
