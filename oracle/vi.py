@@ -1,0 +1,102 @@
+"""FP64 oracle of the variational-inference step (TEST INFRASTRUCTURE ONLY).
+
+Sec. 2.4: a multivariate normal surrogate q = N(mu, Sigma) in unconstrained space is fitted
+to the posterior p~(z | I_obs) by minimising the ELBO loss E_q[log q(z) - log p~(I_obs, z)]
+with Adam; Sigma = L L^T through a Cholesky bijector: the d(d+1)/2 unconstrained values fill
+the lower triangle of L row by row and the diagonal entries are exponentiated. Initial state
+mu = the MAP point, Sigma = 1e-6 I; the learning rate rises from 0 to its maximum with a
+quadratic polynomial schedule over the first iterations (Table 1: 0 -> 1e-3 over 500).
+
+Gradient estimator (a reading, see the design notes): the pathwise (reparameterisation)
+form. With z = mu + L eps, eps ~ N(0, I), the loss is E[f(z)] - sum_i log L_ii - (d/2)
+(1 + log 2 pi), f = -log p~(z | I), so its gradients are E[grad f] for mu,
+E[(grad f)_i eps_j] for the off-diagonal L_ij (i > j), and L_ii E[(grad f)_i eps_i] - 1 for
+the log-diagonal entries. The expectation is the mean over the n_VI draws of one iteration
+(draws with a non-finite objective are left out of the mean).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import rng
+from .fit import adam_step, objective_and_grad
+
+
+def n_chol(d: int) -> int:
+    return d * (d + 1) // 2
+
+
+def tril_index(d: int):
+    """Row-major positions (i, j), i >= j, of the unconstrained vector's entries."""
+    return np.tril_indices(d)
+
+
+def cholesky_factor(v, d):
+    """Cholesky bijector: vector [d(d+1)/2] -> lower-triangular L with exp on the diagonal."""
+    L = np.zeros((d, d))
+    L[tril_index(d)] = np.asarray(v, np.float64)
+    L[np.diag_indices(d)] = np.exp(np.diag(L))
+    return L
+
+
+def cholesky_inverse(L):
+    """Inverse of the bijector: lower-triangular L with a positive diagonal -> vector."""
+    L = np.array(L, np.float64)
+    L[np.diag_indices(L.shape[0])] = np.log(np.diag(L))
+    return L[tril_index(L.shape[0])]
+
+
+def learning_rate(k, lr_max, warmup):
+    """Polynomial schedule of power 2 from 0 to lr_max over `warmup` iterations (the form
+    of a polynomial decay from init 0 to end lr_max): lr_max (1 - (1 - k/warmup)^2), then
+    constant."""
+    if warmup <= 0:
+        return lr_max
+    frac = 1.0 - min(k, warmup) / warmup
+    return lr_max * (1.0 - frac * frac)
+
+
+def draws(seed, d, n, k):
+    """The n x d standard normals of iteration k: counter (sample, parameter, k, tag)."""
+    s = np.arange(n)[:, None]
+    j = np.arange(d)[None, :]
+    return rng.normals(seed, s, j, np.full((1, 1), k), 0x76690000)
+
+
+def loss_and_grad_fn(fg, mu, v, eps):
+    """ELBO loss and its gradient w.r.t. (mu, v) for a target given by fg(z) -> (f, grad f)
+    rows, with the standard-normal draws eps [n, d]."""
+    mu = np.asarray(mu, np.float64)
+    d = mu.size
+    L = cholesky_factor(v, d)
+    z = mu[None, :] + eps @ L.T
+    f, g = fg(z)
+    ok = np.isfinite(f) & np.all(np.isfinite(g), axis=1)
+    n = int(ok.sum())
+    f, g, e = f[ok], g[ok], eps[ok]
+    loss = f.sum() / n - np.log(np.diag(L)).sum() - 0.5 * d * (1.0 + math.log(2.0 * math.pi))
+    g_mu = g.sum(axis=0) / n
+    gL = g.T @ e / n  # [i, j] = mean of g_i eps_j
+    gv = gL.copy()
+    gv[np.diag_indices(d)] = np.diag(L) * np.diag(gL) - 1.0
+    return loss, g_mu, gv[tril_index(d)], n
+
+
+def loss_and_grad(model, mu, v, eps, obs, priors):
+    """loss_and_grad_fn on the lens posterior in unconstrained space."""
+    def fg(z):
+        f, g, _ = objective_and_grad(model, z, obs, priors)
+        return f, g
+    return loss_and_grad_fn(fg, mu, v, eps)
+
+
+def vi_step(fg, mu, v, m, s, k, eps, lr, beta1=0.9, beta2=0.999, adam_eps=1e-8):
+    """One VI iteration: the loss gradient at (mu, v) with draws eps, then Adam (moments
+    m, s over the concatenated (mu, v)) at 0-based step k with learning rate lr."""
+    loss, g_mu, g_v, _ = loss_and_grad_fn(fg, mu, v, eps)
+    x = np.concatenate([mu, v])
+    x, m, s = adam_step(x, m, s, np.concatenate([g_mu, g_v]), k, lr, beta1, beta2, adam_eps)
+    d = len(mu)
+    return x[:d], x[d:], m, s, loss

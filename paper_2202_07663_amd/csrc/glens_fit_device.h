@@ -31,9 +31,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-// Uniform double in (0, 1) from two 32-bit words (53 random bits).
+// Uniform double in (0, 1) from two 32-bit words: 52 random bits k (26 from each word),
+// u = (k + 1/2) / 2^52, where k + 1/2 is exact so that u never rounds to 0 or 1.
 __device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
-  return (double((a >> 5)) * 67108864.0 + double(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+  return (double(a >> 6) * 67108864.0 + double(b >> 6) + 0.5) * (1.0 / 4503599627370496.0);
 }
 
 __device__ __forceinline__ double std_normal_cdf(double x) { return 0.5 * erfc(-x * 0.7071067811865476); }
