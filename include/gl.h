@@ -151,6 +151,7 @@ typedef struct gl_fit_result {
   int d;                  /* number of parameters */
   int best;               /* index of the best particle */
   float theta_best[GL_MAX_PARAMS];
+  float z_best[GL_MAX_PARAMS];  /* the same particle in unconstrained space (g^-1) */
   double logl_best;       /* log L at theta_best */
   double logpost_best;    /* log L + log p + log|J| at the best particle's z */
   double chi2nu;          /* chi^2 / (H W - d) at theta_best */
@@ -181,6 +182,58 @@ int gl_fit_state_store(gl_fit_state* st, float* z, float* m, float* v, int* step
 int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Variational inference (Sec. 2.4): a multivariate normal surrogate q = N(mu, Sigma) of the
+ * posterior in unconstrained space (the fit's target), fitted by minimising the ELBO loss
+ * E_q[log q - log p~(I, z)] with Adam. Sigma = L L^T through the Cholesky bijector: d(d+1)/2
+ * values v fill the lower triangle of L row by row (v[i(i+1)/2 + j] is L_ij) and the diagonal
+ * is exponentiated. The state x = (mu [d], v [d(d+1)/2]) starts at (mu0, log(init_sd) on the
+ * diagonal, 0 elsewhere), i.e. Sigma = init_sd^2 I (the paper: the MAP point and 1e-6 I).
+ * Iteration k draws n_samples eps ~ N(0, I) (Philox4x32-10 keyed by seed, counter
+ * (sample, parameter, k, 0x76690000); uniforms u = (k52 + 1/2) / 2^52 from 26 + 26 bits of
+ * two words; Box-Muller cosine branch), evaluates the likelihood gradient at z = mu + L eps
+ * for all samples in one batched launch, and takes the pathwise gradient estimate: the mean
+ * over samples with a finite objective f = -log p~(z | I) of grad f for mu, of
+ * (grad f)_i eps_j for L_ij (i > j), and of L_ii (grad f)_i eps_i - 1 for v_ii. (The paper
+ * prints the score-function form of the same gradient; both estimate it without bias.)
+ * Adam (beta1, beta2, eps; 0.9, 0.999, 1e-8 if all are 0) then steps x with learning rate
+ * lr_max (1 - (1 - min(k, lr_warmup) / lr_warmup)^2) (the paper: 1e-3, warm-up 500).
+ * ------------------------------------------------------------------------------------- */
+typedef struct gl_vi_opts {
+  int n_samples;          /* n_VI, >= 1 */
+  int K;                  /* iterations, >= 1 */
+  float lr_max;           /* >= 0 */
+  int lr_warmup;          /* >= 0 (0: constant lr_max) */
+  float beta1, beta2, eps;
+  float init_sd;          /* > 0 */
+  uint64_t seed;
+  const gl_prior* priors; /* host [d], copied */
+} gl_vi_opts;
+
+typedef struct gl_vi gl_vi;
+/* Create the state on `model` (with an observed image); mu0: device [d] FP64 (copied). The
+ * state holds (4 (d + d(d+1)/2) + n_samples (d + 1) + K) doubles and 2 n_samples d floats;
+ * it uses the model's workspace (the model must outlive it; order calls on one stream). */
+int gl_vi_create(gl_model* model, const gl_vi_opts* opts, const double* mu0, gl_vi** out,
+                 void* stream);
+int gl_vi_destroy(gl_vi* v);
+/* Run the next n iterations on `stream`; GL_E_INVALID if fewer than n of K are left. An
+ * iteration with no finite sample leaves the state as it was and records a NaN loss. */
+int gl_vi_step(gl_vi* v, int n, void* stream);
+/* Current mean (device [d]), dense Cholesky factor L and covariance L L^T (device [d][d]
+ * row-major), all FP64; any may be NULL. */
+int gl_vi_get(gl_vi* v, double* mu, double* chol, double* cov, void* stream);
+/* n draws from the current surrogate, z = mu + L eps (device [n][d] FP64), eps from counter
+ * (draw, parameter, 0, 0x76697371) under `seed` (e.g. HMC chain starts, as in the paper). */
+int gl_vi_sample(gl_vi* v, int n, uint64_t seed, double* z, void* stream);
+/* The optimiser state: x = (mu, v), Adam moments m and s (device [d + d(d+1)/2] FP64), the
+ * iteration count k, and the loss history (device [K] FP64, NaN where not run); any pointer
+ * may be NULL. set_state loads x, m, s and k (k <= K). */
+int gl_vi_get_state(gl_vi* v, double* x, double* m, double* s, int* k, double* loss,
+                    void* stream);
+int gl_vi_set_state(gl_vi* v, const double* x, const double* m, const double* s, int k,
+                    void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Preconditioned Hamiltonian Monte Carlo (Sec. 2.5): `chains` independent chains on the
  * posterior in unconstrained space, log p~(z | I) = log L(g(z)) + log p~(z) (the fit's
  * target), momenta p ~ N(0, M) for a mass matrix M given by its inverse (the paper sets M
@@ -195,6 +248,8 @@ int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
  * gradient launch over all chains. Random numbers: Philox4x32-10 keyed by `seed`, counter
  * (chain, parameter, trajectory, purpose).
  * ------------------------------------------------------------------------------------- */
+enum { GL_MASS_DIAG = 0, GL_MASS_DENSE = 1, GL_MASS_CHOL = 2 };
+
 typedef struct gl_hmc_opts {
   int chains;                  /* >= 1 */
   int n_leapfrog;              /* L, >= 1 */
@@ -203,10 +258,12 @@ typedef struct gl_hmc_opts {
   float target_accept;         /* in (0, 1) */
   float adapt_frac;            /* share of burn-in with step-size adaptation, in [0, 1] */
   uint64_t seed;
-  const float* inv_mass;       /* host, copied: M^-1, NULL for the identity; the diagonal [d]
-                                  (> 0) or, with inv_mass_dense, the full symmetric positive
-                                  definite [d][d] row-major (e.g. a posterior covariance of z) */
-  int inv_mass_dense;
+  const float* inv_mass;       /* host, copied: M^-1, NULL for the identity; see form */
+  int inv_mass_form;           /* GL_MASS_DIAG: inv_mass is the diagonal [d] (> 0);
+                                  GL_MASS_DENSE: the full symmetric positive definite [d][d]
+                                  row-major (e.g. a posterior covariance of z);
+                                  GL_MASS_CHOL: its lower Cholesky factor [d][d] row-major
+                                  (positive diagonal; entries above it are ignored) */
   const gl_prior* priors;      /* host [d], copied */
 } gl_hmc_opts;
 

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import GlError, check, lib
 
-__all__ = ["Model", "LogLik", "FitState", "fit", "HMC", "Server", "GlError", "param_names", "nparams",
+__all__ = ["Model", "LogLik", "FitState", "fit", "VI", "HMC", "Server", "GlError", "param_names", "nparams",
            "make_priors", "make_fit_opts", "result_dict"]
 
 
@@ -197,7 +197,8 @@ def make_fit_opts(P, K, priors, lr0=1e-2, lr1=1e-3, seed=0, beta1=0.9, beta2=0.9
 
 def result_dict(r) -> dict:
     return {"status": r.status, "d": r.d, "best": r.best,
-            "theta_best": np.array(r.theta_best[:r.d], np.float32), "logl_best": r.logl_best,
+            "theta_best": np.array(r.theta_best[:r.d], np.float32),
+            "z_best": np.array(r.z_best[:r.d], np.float32), "logl_best": r.logl_best,
             "logpost_best": r.logpost_best, "chi2nu": r.chi2nu, "t_submit": r.t_submit,
             "t_admit": r.t_admit, "t_done": r.t_done}
 
@@ -261,6 +262,82 @@ def fit(model: Model, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0, stream
 
 
 # ------------------------------------------------------------------------------------------
+# Variational inference (Sec. 2.4)
+# ------------------------------------------------------------------------------------------
+class VI:
+    """Multivariate normal surrogate of one system's posterior in unconstrained space, fitted
+    by the library's kernels (one batched likelihood-gradient launch per iteration).
+    mu0: [d] start of the mean (the paper: the MAP point, e.g. fit(...)["z_best"])."""
+
+    def __init__(self, model: Model, n_samples: int, K: int, priors, mu0, lr_max: float = 1e-3,
+                 lr_warmup: int = 500, init_sd: float = 1e-3, seed: int = 0, beta1=0.9,
+                 beta2=0.999, eps=1e-8, stream=None):
+        assert len(priors) == model.d
+        self.model, self.n, self.K, self.d = model, n_samples, K, model.d
+        self._pa = make_priors(priors)
+        o = _lib.ViOpts(n_samples=n_samples, K=K, lr_max=lr_max, lr_warmup=lr_warmup,
+                        beta1=beta1, beta2=beta2, eps=eps, init_sd=init_sd, seed=seed,
+                        priors=self._pa)
+        mu = torch.as_tensor(np.asarray(mu0, np.float64)).reshape(model.d).cuda()
+        h = ctypes.c_void_p()
+        check(lib().gl_vi_create(model._h, ctypes.byref(o), mu.data_ptr(), ctypes.byref(h),
+                                 _stream_ptr(stream)))
+        self._h = h
+        torch.cuda.synchronize()
+
+    @property
+    def nx(self) -> int:
+        return self.d + self.d * (self.d + 1) // 2
+
+    def step(self, n: int | None = None, stream=None):
+        """Run the next n iterations (all that are left by default)."""
+        if n is None:
+            n = self.K - self.get_state(stream)["k"]
+        check(lib().gl_vi_step(self._h, n, _stream_ptr(stream)))
+
+    def get(self, stream=None) -> dict:
+        """mean [d], Cholesky factor [d, d] and covariance [d, d] (cuda float64)."""
+        d = self.d
+        mu = torch.empty(d, dtype=torch.float64, device="cuda")
+        chol = torch.empty((d, d), dtype=torch.float64, device="cuda")
+        cov = torch.empty((d, d), dtype=torch.float64, device="cuda")
+        check(lib().gl_vi_get(self._h, mu.data_ptr(), chol.data_ptr(), cov.data_ptr(),
+                              _stream_ptr(stream)))
+        return {"mu": mu, "chol": chol, "cov": cov}
+
+    def sample(self, n: int, seed: int = 0, stream=None) -> torch.Tensor:
+        z = torch.empty((n, self.d), dtype=torch.float64, device="cuda")
+        check(lib().gl_vi_sample(self._h, n, seed, z.data_ptr(), _stream_ptr(stream)))
+        return z
+
+    def get_state(self, stream=None) -> dict:
+        x, m, s = (torch.empty(self.nx, dtype=torch.float64, device="cuda") for _ in range(3))
+        loss = torch.empty(self.K, dtype=torch.float64, device="cuda")
+        k = ctypes.c_int()
+        check(lib().gl_vi_get_state(self._h, x.data_ptr(), m.data_ptr(), s.data_ptr(),
+                                    ctypes.byref(k), loss.data_ptr(), _stream_ptr(stream)))
+        return {"x": x, "m": m, "s": s, "k": k.value, "loss": loss}
+
+    def set_state(self, x, m, s, k: int, stream=None):
+        x, m, s = (torch.as_tensor(t, dtype=torch.float64).reshape(self.nx).cuda().contiguous()
+                   for t in (x, m, s))
+        check(lib().gl_vi_set_state(self._h, x.data_ptr(), m.data_ptr(), s.data_ptr(), k,
+                                    _stream_ptr(stream)))
+        self._keep = (x, m, s)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gl_vi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------
 # Preconditioned Hamiltonian Monte Carlo (Sec. 2.5)
 # ------------------------------------------------------------------------------------------
 class HMC:
@@ -268,12 +345,13 @@ class HMC:
     library's kernels (one batched likelihood-gradient launch per leapfrog step).
     z0: optional [chains, d] unconstrained starts (e.g. the fit's best particle plus
     jitter; kept in FP64); inv_mass: optional inverse mass matrix M^-1, the diagonal [d] or the full
-    [d, d] (the paper uses the variational posterior covariance of z)."""
+    [d, d] (the paper uses the variational posterior covariance of z); mass_chol: instead, the
+    lower Cholesky factor of M^-1 (e.g. VI.get()["chol"])."""
 
     def __init__(self, model: Model, chains: int, n_leapfrog: int, n_burn: int, n_samples: int,
                  priors, step_size: float = 1e-2, target_accept: float = 0.75,
                  adapt_frac: float = 0.8, seed: int = 0, z0: torch.Tensor | None = None,
-                 inv_mass=None, stream=None):
+                 inv_mass=None, mass_chol=None, stream=None):
         assert len(priors) == model.d
         self.model, self.C = model, chains
         self.n_burn, self.n_samples = n_burn, n_samples
@@ -281,12 +359,14 @@ class HMC:
         o = _lib.HmcOpts(chains=chains, n_leapfrog=n_leapfrog, n_burn=n_burn,
                          n_samples=n_samples, step_size=step_size, target_accept=target_accept,
                          adapt_frac=adapt_frac, seed=seed, priors=self._pa)
-        if inv_mass is not None:
-            im = np.ascontiguousarray(np.asarray(inv_mass, np.float32))
+        if inv_mass is not None or mass_chol is not None:
+            assert inv_mass is None or mass_chol is None
+            im = np.ascontiguousarray(np.asarray(inv_mass if mass_chol is None else mass_chol,
+                                                 np.float32))
             assert im.shape in ((model.d,), (model.d, model.d))
             self._im = (ctypes.c_float * im.size)(*im.ravel().tolist())
             o.inv_mass = self._im
-            o.inv_mass_dense = int(im.ndim == 2)
+            o.inv_mass_form = 2 if mass_chol is not None else int(im.ndim == 2)
         zp = None
         if z0 is not None:
             z0 = z0.to(torch.float64).contiguous()

@@ -46,7 +46,8 @@ class FitOpts(ctypes.Structure):
 
 class FitResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("d", ctypes.c_int), ("best", ctypes.c_int),
-                ("theta_best", ctypes.c_float * GL_MAX_PARAMS), ("logl_best", ctypes.c_double),
+                ("theta_best", ctypes.c_float * GL_MAX_PARAMS),
+                ("z_best", ctypes.c_float * GL_MAX_PARAMS), ("logl_best", ctypes.c_double),
                 ("logpost_best", ctypes.c_double), ("chi2nu", ctypes.c_double),
                 ("t_submit", ctypes.c_uint64), ("t_admit", ctypes.c_uint64),
                 ("t_done", ctypes.c_uint64)]
@@ -57,12 +58,20 @@ class HmcOpts(ctypes.Structure):
                 ("n_samples", ctypes.c_int), ("step_size", ctypes.c_float),
                 ("target_accept", ctypes.c_float), ("adapt_frac", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("inv_mass", ctypes.POINTER(ctypes.c_float)),
-                ("inv_mass_dense", ctypes.c_int), ("priors", ctypes.POINTER(Prior))]
+                ("inv_mass_form", ctypes.c_int), ("priors", ctypes.POINTER(Prior))]
 
 
 class HmcInfo(ctypes.Structure):
     _fields_ = [("step_size", ctypes.c_float), ("accept_mean", ctypes.c_double),
                 ("trajectories", ctypes.c_int)]
+
+
+class ViOpts(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int), ("K", ctypes.c_int), ("lr_max", ctypes.c_float),
+                ("lr_warmup", ctypes.c_int), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("init_sd", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("priors", ctypes.POINTER(Prior))]
 
 
 class ServerOpts(ctypes.Structure):
@@ -100,6 +109,13 @@ _SIGNATURES = {
     "gl_hmc_samples": [_vp, _vp, _vp],
     "gl_hmc_get_info": [_vp, ctypes.POINTER(HmcInfo), _vp],
     "gl_hmc_leapfrog": [_vp, _vp, _vp, _i, ctypes.c_float, _vp, _vp, _vp, _vp],
+    "gl_vi_create": [_vp, ctypes.POINTER(ViOpts), _vp, ctypes.POINTER(_vp), _vp],
+    "gl_vi_destroy": [_vp],
+    "gl_vi_step": [_vp, _i, _vp],
+    "gl_vi_get": [_vp, _vp, _vp, _vp, _vp],
+    "gl_vi_sample": [_vp, _i, ctypes.c_uint64, _vp, _vp],
+    "gl_vi_get_state": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i), _vp, _vp],
+    "gl_vi_set_state": [_vp, _vp, _vp, _vp, _i, _vp],
     "gl_server_create": [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)],
     "gl_server_destroy": [_vp],
     "gl_submit": [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(FitOpts),

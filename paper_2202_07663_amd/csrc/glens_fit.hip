@@ -240,6 +240,8 @@ int fit_result_from_device(const FitBuffers& fb, const Workspace& ws, int P, con
   double ll = 0.0;
   GL_HIP(hipMemcpyAsync(out->theta_best, ws.theta + size_t(best) * c.d, sizeof(float) * c.d,
                         hipMemcpyDeviceToHost, st));
+  GL_HIP(hipMemcpyAsync(out->z_best, fb.z + size_t(best) * c.d, sizeof(float) * c.d,
+                        hipMemcpyDeviceToHost, st));
   GL_HIP(hipMemcpyAsync(&ll, ws.logl + best, sizeof(double), hipMemcpyDeviceToHost, st));
   GL_HIP(hipStreamSynchronize(st));
   out->status = GL_OK;

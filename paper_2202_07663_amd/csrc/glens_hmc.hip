@@ -386,23 +386,35 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   std::vector<Prior> pri;
   int rc = validate_fit_opts(&fo, d, pri);
   if (rc) return rc;
-  // M^-1 = S = chol chol^T (identity, diagonal or dense), factored in double on the host.
+  // M^-1 = S = chol chol^T (identity, diagonal, dense or given as its factor), factored in
+  // double on the host.
+  const int form = o->inv_mass ? o->inv_mass_form : GL_MASS_DIAG;
+  if (form != GL_MASS_DIAG && form != GL_MASS_DENSE && form != GL_MASS_CHOL)
+    return set_error(GL_E_INVALID, "unknown inv_mass_form %d", form);
   std::vector<double> S(size_t(d) * d, 0.0);
-  for (int j = 0; j < d; ++j) {
-    double v = 1.0;
-    if (o->inv_mass && !o->inv_mass_dense) v = o->inv_mass[j];
-    S[size_t(j) * d + j] = v;
-  }
-  if (o->inv_mass && o->inv_mass_dense) {
+  if (form == GL_MASS_DIAG) {
+    for (int j = 0; j < d; ++j) S[size_t(j) * d + j] = o->inv_mass ? o->inv_mass[j] : 1.0;
+  } else {
     for (int i = 0; i < d; ++i)
       for (int j = 0; j < d; ++j) {
         const double v = o->inv_mass[i * d + j], vt = o->inv_mass[j * d + i];
-        if (!std::isfinite(v) || std::fabs(v - vt) > 1e-6 * (std::fabs(v) + std::fabs(vt)))
-          return set_error(GL_E_INVALID, "inv_mass must be finite and symmetric");
-        S[size_t(i) * d + j] = v;
+        if (form == GL_MASS_CHOL) {
+          if (j <= i && !std::isfinite(v)) return set_error(GL_E_INVALID, "inv_mass must be finite");
+          S[size_t(i) * d + j] = j <= i ? v : 0.0;
+        } else {
+          if (!std::isfinite(v) || std::fabs(v - vt) > 1e-6 * (std::fabs(v) + std::fabs(vt)))
+            return set_error(GL_E_INVALID, "inv_mass must be finite and symmetric");
+          S[size_t(i) * d + j] = v;
+        }
       }
   }
-  if (!cholesky(S, d)) return set_error(GL_E_INVALID, "inv_mass must be positive definite");
+  if (form == GL_MASS_CHOL) {
+    for (int i = 0; i < d; ++i)
+      if (!(S[size_t(i) * d + i] > 0.0))
+        return set_error(GL_E_INVALID, "the Cholesky factor needs a positive diagonal");
+  } else if (!cholesky(S, d)) {
+    return set_error(GL_E_INVALID, "inv_mass must be positive definite");
+  }
   const std::vector<double> SIT = inverse_transpose_lower(S, d);
   std::vector<float> chol(S.begin(), S.end()), chol_it(SIT.begin(), SIT.end());
   if (z0 && (rc = check_device_ptr(z0, "z0"))) return rc;

@@ -1,0 +1,440 @@
+// Variational inference with a multivariate normal surrogate (Sec. 2.4): the gl_vi* C ABI.
+//
+// q = N(mu, Sigma) in unconstrained space, Sigma = L L^T with L from the Cholesky bijector:
+// the n_c = d(d+1)/2 values v fill the lower triangle of L row by row (entry i(i+1)/2 + j
+// is L_ij) and the diagonal is exponentiated. The ELBO loss E_q[log q - log p~(I, z)] is
+// minimised by Adam over x = (mu, v). Each iteration:
+//   draw     one block per sample s: eps_s ~ N(0, I) (Philox, counter (s, j, k, tag)),
+//            z_s = mu + L eps_s, rounded to FP32 for the likelihood pipeline;
+//   pipeline log L and d log L / d theta at g(z_s) for every sample in one batched launch;
+//   grad     one block per sample: f_s = -log p~(z_s | I) and grad f_s (prior, bijector);
+//   update   one lane per entry of x: the pathwise gradient estimate (mean over the samples
+//            with a finite objective, in sample order, FP64) of
+//              mu_i: E[(grad f)_i],  L_ij (i > j): E[(grad f)_i eps_j],
+//              v_ii = log L_ii: L_ii E[(grad f)_i eps_i] - 1,
+//            then Adam at the iteration's learning rate. x is double-buffered so that every
+//            lane reads the iteration's old state; lane 0 also records the loss
+//            E[f] - sum_i log L_ii - (d/2)(1 + log 2 pi).
+// The learning rate rises from 0 to lr_max as lr_max (1 - (1 - k / warmup)^2) over the
+// first `warmup` iterations (the paper: 0 -> 1e-3 over 500), then stays at lr_max.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "glens_device.h"
+#include "glens_fit.h"
+#include "glens_fit_device.h"
+#include "glens_host.h"
+
+namespace glens {
+
+constexpr int kViThreads = 64;
+constexpr uint32_t kViDrawTag = 0x76690000u;
+constexpr uint32_t kViSampleTag = 0x76697371u;
+
+struct ViArgs {
+  int n, d, nc, k;
+  float lr;
+  float beta1, beta2, adam_eps;
+  const Prior* prior;
+  const double* x;     // [d + nc] current (mu, v)
+  double* x_new;       // [d + nc] next (mu, v)
+  double* m;           // [d + nc] Adam moments
+  double* s;
+  double* eps;         // [n][d] this iteration's draws
+  float* z32;          // [n][d] samples for the pipeline
+  float* g;            // [n][d] grad f
+  double* f;           // [n] f, NaN when not finite
+  const double* logl;  // pipeline outputs
+  const float* grad;
+  const float* theta;
+  double* loss;        // [K] loss history
+  uint32_t seed_lo, seed_hi;
+};
+
+__device__ __forceinline__ double chol_entry(const double* v, int i, int j) {
+  const double e = v[i * (i + 1) / 2 + j];
+  return i == j ? exp(e) : e;
+}
+
+// z = mu + L eps for one sample (block), eps drawn with tag `tag` at iteration `k`.
+__device__ __forceinline__ void draw_sample(const double* mu, const double* v, int d, int s,
+                                            int k, uint32_t tag, uint32_t seed_lo,
+                                            uint32_t seed_hi, double* s_eps, double* eps_out,
+                                            float* z32_out, double* z64_out) {
+  for (int j = threadIdx.x; j < d; j += kViThreads) {
+    uint32_t w[4] = {uint32_t(s), uint32_t(j), uint32_t(k), tag};
+    philox4x32_10(w, seed_lo, seed_hi);
+    const double u1 = u01(w[0], w[1]), u2 = u01(w[2], w[3]);
+    const double e = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    s_eps[j] = e;
+    if (eps_out) eps_out[size_t(s) * d + j] = e;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += kViThreads) {
+    double zi = mu[i];
+    for (int j = 0; j <= i; ++j) zi += chol_entry(v, i, j) * s_eps[j];
+    if (z32_out) z32_out[size_t(s) * d + i] = float(zi);
+    if (z64_out) z64_out[size_t(s) * d + i] = zi;
+  }
+}
+
+__global__ void __launch_bounds__(kViThreads) vi_draw_kernel(ViArgs a) {
+  __shared__ double s_eps[kMaxParams];
+  draw_sample(a.x, a.x + a.d, a.d, blockIdx.x, a.k, kViDrawTag, a.seed_lo, a.seed_hi, s_eps,
+              a.eps, a.z32, nullptr);
+}
+
+// f = -log p~(z | I) and its gradient for one sample (terms summed in parameter order).
+__global__ void __launch_bounds__(kViThreads) vi_grad_kernel(ViArgs a) {
+  __shared__ double s_t[kMaxParams];
+  __shared__ int s_bad;
+  const int c = blockIdx.x;
+  const size_t row = size_t(c) * a.d;
+  int bad_lane = 0;
+  for (int j = threadIdx.x; j < a.d; j += kViThreads) {
+    float dlp, dth;
+    s_t[j] = log_prior_z(a.prior[j], a.z32[row + j], a.theta[row + j], dlp, dth);
+    const float gj = -(a.grad[row + j] * dth + dlp);
+    a.g[row + j] = gj;
+    bad_lane |= !isfinite(gj);
+  }
+  const int bad_any = __any(bad_lane);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lp = a.logl[c];
+    for (int j = 0; j < a.d; ++j) lp += s_t[j];
+    s_bad = bad_any || !isfinite(lp);
+    a.f[c] = s_bad ? NAN : -lp;
+  }
+}
+
+// Gradient estimate and Adam update of one entry of x (and the loss, lane 0).
+__global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int d = a.d, nx = a.d + a.nc;
+  if (q >= nx) return;
+  const double* v = a.x + d;
+  int i, j;
+  if (q < d) {
+    i = q;
+    j = -1;
+  } else {  // row-major lower triangle: r = i(i+1)/2 + j
+    const int r = q - d;
+    i = int((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= r) ++i;
+    while (i * (i + 1) / 2 > r) --i;
+    j = r - i * (i + 1) / 2;
+  }
+  double sum = 0.0, fsum = 0.0;
+  int nok = 0;
+  for (int s = 0; s < a.n; ++s) {
+    const double fs = a.f[s];
+    if (!isfinite(fs)) continue;
+    ++nok;
+    const double gi = a.g[size_t(s) * d + i];
+    sum += j < 0 ? gi : gi * a.eps[size_t(s) * d + j];
+    fsum += fs;
+  }
+  if (nok == 0) {  // no usable sample: keep the state
+    a.x_new[q] = a.x[q];
+    if (q == 0) a.loss[a.k] = NAN;
+    return;
+  }
+  double gq = sum / nok;
+  if (j == i) gq = exp(v[i * (i + 1) / 2 + i]) * gq - 1.0;
+  if (q == 0) {
+    double logdet = 0.0;
+    for (int t = 0; t < d; ++t) logdet += v[t * (t + 1) / 2 + t];
+    a.loss[a.k] = fsum / nok - logdet - 0.5 * d * (1.0 + 1.8378770664093453);
+  }
+  const int t = a.k + 1;
+  const double mq = a.beta1 * a.m[q] + (1.0 - a.beta1) * gq;
+  const double sq = a.beta2 * a.s[q] + (1.0 - a.beta2) * gq * gq;
+  a.m[q] = mq;
+  a.s[q] = sq;
+  const double mhat = mq / (1.0 - pow(double(a.beta1), t));
+  const double shat = sq / (1.0 - pow(double(a.beta2), t));
+  a.x_new[q] = a.x[q] - a.lr * mhat / (sqrt(shat) + a.adam_eps);
+}
+
+// Draws from the surrogate: z_s = mu + L eps_s (FP64), counter (s, j, 0, tag).
+__global__ void __launch_bounds__(kViThreads) vi_sample_kernel(ViArgs a, double* z) {
+  __shared__ double s_eps[kMaxParams];
+  draw_sample(a.x, a.x + a.d, a.d, blockIdx.x, 0, kViSampleTag, a.seed_lo, a.seed_hi, s_eps,
+              nullptr, nullptr, z);
+}
+
+// Dense L (lower, [d][d]) and Sigma = L L^T ([d][d]); either may be NULL.
+__global__ void __launch_bounds__(256) vi_dense_kernel(const double* x, int d, double* chol,
+                                                       double* cov) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d * d) return;
+  const int i = q / d, j = q - i * d;
+  const double* v = x + d;
+  if (chol) chol[q] = j <= i ? chol_entry(v, i, j) : 0.0;
+  if (cov) {
+    double c = 0.0;
+    const int kmax = i < j ? i : j;
+    for (int k = 0; k <= kmax; ++k) c += chol_entry(v, i, k) * chol_entry(v, j, k);
+    cov[q] = c;
+  }
+}
+
+}  // namespace glens
+
+using namespace glens;
+
+#define GL_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
+                       #call, hipGetErrorString(e_));                                    \
+  } while (0)
+
+struct gl_vi {
+  gl_model* model = nullptr;
+  int n = 0, d = 0, nc = 0, K = 0, k = 0, cur = 0, warmup = 0;
+  float lr_max = 0.f;
+  char* base = nullptr;
+  double* x[2] = {nullptr, nullptr};
+  ViArgs a{};
+  FitBuffers fb;  // holds the priors
+};
+
+static int vi_check_launch() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
+}
+
+static float vi_learning_rate(const gl_vi* v, int k) {
+  if (v->warmup <= 0) return v->lr_max;
+  const double frac = 1.0 - double(std::min(k, v->warmup)) / v->warmup;
+  return float(v->lr_max * (1.0 - frac * frac));
+}
+
+static int vi_iteration(gl_vi* v, hipStream_t st) {
+  gl_model* m = v->model;
+  const ModelCfg& c = m->sys.cfg;
+  const int tiles = choose_tiles(v->n, c.H * c.W);
+  int rc = workspace_reserve(m->ws, v->n, tiles, c.H * c.W, c.d, true);
+  if (rc) return rc;
+  ViArgs& a = v->a;
+  a.k = v->k;
+  a.lr = vi_learning_rate(v, v->k);
+  a.x = v->x[v->cur];
+  a.x_new = v->x[1 - v->cur];
+  a.logl = m->ws.logl;
+  a.grad = m->ws.grad;
+  a.theta = m->ws.theta;
+  hipLaunchKernelGGL(vi_draw_kernel, dim3(v->n), dim3(kViThreads), 0, st, a);
+  if ((rc = vi_check_launch())) return rc;
+  Group g;
+  std::memset(&g, 0, sizeof(g));
+  g.nsys = 1;
+  g.sys[0] = make_sys(m->sys, m->ws, v->n, tiles);
+  g.sys[0].theta = nullptr;
+  g.sys[0].z = a.z32;
+  g.sys[0].prior = v->fb.prior;
+  g.sys[0].theta_out = m->ws.theta;
+  g.sys[0].logl = m->ws.logl;
+  g.sys[0].grad = m->ws.grad;
+  if ((rc = run_group(g, subpix_key(c), c.K, 2, st))) return rc;
+  hipLaunchKernelGGL(vi_grad_kernel, dim3(v->n), dim3(kViThreads), 0, st, a);
+  if ((rc = vi_check_launch())) return rc;
+  const int nx = v->d + v->nc;
+  hipLaunchKernelGGL(vi_update_kernel, dim3((nx + 255) / 256), dim3(256), 0, st, a);
+  if ((rc = vi_check_launch())) return rc;
+  v->cur = 1 - v->cur;
+  v->k++;
+  return GL_OK;
+}
+
+extern "C" {
+
+int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** out,
+                 void* stream) {
+  clear_error();
+  if (!out) return set_error(GL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!m || !o || !mu0) return set_error(GL_E_INVALID, "NULL argument");
+  if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
+  if (o->n_samples < 1 || o->K < 1 || o->lr_warmup < 0)
+    return set_error(GL_E_INVALID, "need n_samples >= 1, K >= 1, lr_warmup >= 0");
+  if (!(o->lr_max >= 0.f) || !std::isfinite(o->lr_max))
+    return set_error(GL_E_INVALID, "lr_max must be finite and >= 0");
+  if (!(o->init_sd > 0.f) || !std::isfinite(o->init_sd))
+    return set_error(GL_E_INVALID, "init_sd must be > 0");
+  const ModelCfg& c = m->sys.cfg;
+  const int d = c.d, nc = d * (d + 1) / 2, n = o->n_samples, nx = d + nc;
+  gl_fit_opts fo;
+  std::memset(&fo, 0, sizeof(fo));
+  fo.P = n;
+  fo.K = 1;
+  fo.priors = o->priors;
+  std::vector<Prior> pri;
+  int rc = validate_fit_opts(&fo, d, pri);
+  if (rc) return rc;
+  if ((rc = check_device_ptr(mu0, "mu0"))) return rc;
+  gl_vi* v = new (std::nothrow) gl_vi();
+  if (!v) return set_error(GL_E_NOMEM, "host allocation failed");
+  v->model = m;
+  v->n = n;
+  v->d = d;
+  v->nc = nc;
+  v->K = o->K;
+  v->warmup = o->lr_warmup;
+  v->lr_max = o->lr_max;
+  hipStream_t st = (hipStream_t)stream;
+  rc = workspace_reserve(m->ws, n, choose_tiles(n, c.H * c.W), c.H * c.W, d, true);
+  if (!rc) rc = fit_buffers_alloc(v->fb, n, d, pri.data());
+  const size_t nd = size_t(n) * d;
+  const size_t bytes = sizeof(double) * (4 * size_t(nx) + nd + n + o->K) +
+                       sizeof(float) * 2 * nd + 256 * 12;
+  if (!rc && hipMalloc(&v->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
+  if (rc) {
+    fit_buffers_free(v->fb);
+    delete v;
+    return rc;
+  }
+  char* q = v->base;
+  auto take = [&](size_t b) {
+    char* r = q;
+    q += (b + 255) & ~size_t(255);
+    return r;
+  };
+  v->x[0] = reinterpret_cast<double*>(take(sizeof(double) * nx));
+  v->x[1] = reinterpret_cast<double*>(take(sizeof(double) * nx));
+  ViArgs& a = v->a;
+  a.n = n;
+  a.d = d;
+  a.nc = nc;
+  a.prior = v->fb.prior;
+  a.m = reinterpret_cast<double*>(take(sizeof(double) * nx));
+  a.s = reinterpret_cast<double*>(take(sizeof(double) * nx));
+  a.eps = reinterpret_cast<double*>(take(sizeof(double) * nd));
+  a.f = reinterpret_cast<double*>(take(sizeof(double) * n));
+  a.loss = reinterpret_cast<double*>(take(sizeof(double) * o->K));
+  a.z32 = reinterpret_cast<float*>(take(sizeof(float) * nd));
+  a.g = reinterpret_cast<float*>(take(sizeof(float) * nd));
+  const bool defaults = o->beta1 == 0.f && o->beta2 == 0.f && o->eps == 0.f;
+  a.beta1 = defaults ? 0.9f : o->beta1;
+  a.beta2 = defaults ? 0.999f : o->beta2;
+  a.adam_eps = defaults ? 1e-8f : o->eps;
+  a.seed_lo = uint32_t(o->seed);
+  a.seed_hi = uint32_t(o->seed >> 32);
+  // x = (mu0, v) with L = init_sd I: v_ii = log(init_sd), off-diagonal 0; moments 0
+  std::vector<double> x0(nx, 0.0);
+  for (int i = 0; i < d; ++i) x0[d + i * (i + 1) / 2 + i] = std::log(double(o->init_sd));
+  std::vector<double> zero(nx, 0.0), nan_loss(o->K, NAN);
+  bool ok = hipMemcpy(v->x[0] + d, x0.data() + d, sizeof(double) * nc, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.m, zero.data(), sizeof(double) * nx, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.s, zero.data(), sizeof(double) * nx, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(a.loss, nan_loss.data(), sizeof(double) * o->K, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpyAsync(v->x[0], mu0, sizeof(double) * d, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (!ok) {
+    (void)hipFree(v->base);
+    fit_buffers_free(v->fb);
+    delete v;
+    return set_error(GL_E_DEVICE, "upload failed");
+  }
+  *out = v;
+  return GL_OK;
+}
+
+int gl_vi_destroy(gl_vi* v) {
+  clear_error();
+  if (!v) return GL_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(v->base);
+  fit_buffers_free(v->fb);
+  delete v;
+  return GL_OK;
+}
+
+int gl_vi_step(gl_vi* v, int n, void* stream) {
+  clear_error();
+  if (!v) return set_error(GL_E_INVALID, "state is NULL");
+  if (n < 0 || v->k + n > v->K)
+    return set_error(GL_E_INVALID, "%d iterations requested, %d left", n, v->K - v->k);
+  for (int i = 0; i < n; ++i) {
+    int rc = vi_iteration(v, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GL_OK;
+}
+
+int gl_vi_get(gl_vi* v, double* mu, double* chol, double* cov, void* stream) {
+  clear_error();
+  if (!v) return set_error(GL_E_INVALID, "state is NULL");
+  int rc;
+  if ((mu && (rc = check_device_ptr(mu, "mu"))) || (chol && (rc = check_device_ptr(chol, "chol"))) ||
+      (cov && (rc = check_device_ptr(cov, "cov"))))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const double* x = v->x[v->cur];
+  if (mu) GL_HIP(hipMemcpyAsync(mu, x, sizeof(double) * v->d, hipMemcpyDeviceToDevice, st));
+  if (chol || cov) {
+    const int dd = v->d * v->d;
+    hipLaunchKernelGGL(vi_dense_kernel, dim3((dd + 255) / 256), dim3(256), 0, st, x, v->d, chol,
+                       cov);
+    if ((rc = vi_check_launch())) return rc;
+  }
+  return GL_OK;
+}
+
+int gl_vi_sample(gl_vi* v, int n, uint64_t seed, double* z, void* stream) {
+  clear_error();
+  if (!v) return set_error(GL_E_INVALID, "state is NULL");
+  if (n < 0) return set_error(GL_E_INVALID, "n must be >= 0");
+  if (n == 0) return GL_OK;
+  int rc = check_device_ptr(z, "z");
+  if (rc) return rc;
+  ViArgs a = v->a;
+  a.x = v->x[v->cur];
+  a.seed_lo = uint32_t(seed);
+  a.seed_hi = uint32_t(seed >> 32);
+  hipLaunchKernelGGL(vi_sample_kernel, dim3(n), dim3(kViThreads), 0, (hipStream_t)stream, a, z);
+  return vi_check_launch();
+}
+
+int gl_vi_get_state(gl_vi* v, double* x, double* m, double* s, int* k, double* loss,
+                    void* stream) {
+  clear_error();
+  if (!v) return set_error(GL_E_INVALID, "state is NULL");
+  int rc;
+  if ((x && (rc = check_device_ptr(x, "x"))) || (m && (rc = check_device_ptr(m, "m"))) ||
+      (s && (rc = check_device_ptr(s, "s"))) || (loss && (rc = check_device_ptr(loss, "loss"))))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t b = sizeof(double) * (v->d + v->nc);
+  if (x) GL_HIP(hipMemcpyAsync(x, v->x[v->cur], b, hipMemcpyDeviceToDevice, st));
+  if (m) GL_HIP(hipMemcpyAsync(m, v->a.m, b, hipMemcpyDeviceToDevice, st));
+  if (s) GL_HIP(hipMemcpyAsync(s, v->a.s, b, hipMemcpyDeviceToDevice, st));
+  if (loss) GL_HIP(hipMemcpyAsync(loss, v->a.loss, sizeof(double) * v->K, hipMemcpyDeviceToDevice, st));
+  if (k) *k = v->k;
+  return GL_OK;
+}
+
+int gl_vi_set_state(gl_vi* v, const double* x, const double* m, const double* s, int k,
+                    void* stream) {
+  clear_error();
+  if (!v) return set_error(GL_E_INVALID, "state is NULL");
+  if (k < 0 || k > v->K) return set_error(GL_E_INVALID, "k must be in [0, K]");
+  int rc;
+  if ((rc = check_device_ptr(x, "x")) || (rc = check_device_ptr(m, "m")) ||
+      (rc = check_device_ptr(s, "s")))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t b = sizeof(double) * (v->d + v->nc);
+  GL_HIP(hipMemcpyAsync(v->x[v->cur], x, b, hipMemcpyDeviceToDevice, st));
+  GL_HIP(hipMemcpyAsync(v->a.m, m, b, hipMemcpyDeviceToDevice, st));
+  GL_HIP(hipMemcpyAsync(v->a.s, s, b, hipMemcpyDeviceToDevice, st));
+  v->k = k;
+  return GL_OK;
+}
+
+}  // extern "C"
