@@ -83,6 +83,7 @@ class DualAveraging:
         w = 1.0 / (m + self.t0)
         self.h = (1.0 - w) * self.h + w * (self.target - accept)
         log_eps = self.mu - math.sqrt(m) / self.gamma * self.h
+        log_eps = min(max(log_eps, self.mu - 40.0), self.mu + 40.0)  # no underflow to 0
         eta = m ** (-self.kappa)
         self.log_eps_bar = eta * log_eps + (1.0 - eta) * self.log_eps_bar
         self.eps = math.exp(log_eps)

@@ -221,7 +221,8 @@ __global__ void hmc_adapt_kernel(HmcArgs a) {
     const double m = a.da[3] + 1.0;
     const double w = 1.0 / (m + t0);
     const double h = (1.0 - w) * a.da[1] + w * (a.target - mean);
-    const double log_eps = a.da[0] - sqrt(m) / gamma * h;
+    // kept within e^+-40 of mu so that a run of rejections cannot underflow eps to zero
+    const double log_eps = fmin(fmax(a.da[0] - sqrt(m) / gamma * h, a.da[0] - 40.0), a.da[0] + 40.0);
     const double eta = pow(m, -kappa);
     a.da[1] = h;
     a.da[2] = eta * log_eps + (1.0 - eta) * a.da[2];

@@ -72,6 +72,7 @@ class Spec:
     gain: float = 1.0
     shear: bool = True
     pix: float = PIX
+    dist: str = "workload"  # "paper": the paper's simulation distribution and prior
     names: list = field(default_factory=list)
 
     def __post_init__(self):
@@ -109,6 +110,66 @@ def spec_c2() -> Spec:
     0.065", k = 2, Moffat 21x21 (FWHM 0.15", beta 2.5)."""
     return Spec("epl60", 60, 60, 2, epl=True, lens_light=True, nmax=6,
                 psf=moffat_psf(21, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
+
+
+def spec_paper80() -> Spec:
+    """The configuration of the paper's simulated systems (Sec. 3): EPL + shear, Sersic lens
+    light, Sersic source (22 parameters), 80x80 at 0.065", k = 2, sigma_bkg = 0.2, t_exp =
+    100 s, gain 1. The paper's HST PSF model is not available: a Moffat 21x21 (FWHM 0.15",
+    beta 2.5) stands in for it."""
+    return Spec("paper80", 80, 80, 2, epl=True, lens_light=True, nmax=-1,
+                psf=moffat_psf(21, 0.15, 2.5), sigma_bkg=0.2, t_exp=100.0, dist="paper")
+
+
+# The paper's simulation distribution and (broadened) prior of eq. sim-dist, per parameter
+# in the gl.h order (EPL + shear, Sersic lens light, Sersic source): (family, simulation
+# arguments, prior arguments). ln = log-normal (median, sigma of the log), tn = truncated
+# normal (mean, sigma, low, high), n = normal (mean, sigma), u = uniform (low, high).
+# Reading: the paper's half-light intensities I_l, I_s are surface brightnesses per square
+# arcsecond (with them its arcs have the quoted signal-to-noise of about 100), while the
+# amplitude of this library's Sersic profile is the value of a pixel; PAPER_AMP_INDEX marks
+# the two amplitudes, whose medians are multiplied by the pixel area.
+PAPER_DIST = [
+    ("ln", (1.25, 0.25), (1.25, 0.4)),             # theta_E
+    ("tn", (2.0, 0.25, 1.0, 3.0), (2.0, 0.5, 1.0, 3.0)),  # gamma_epl
+    ("n", (0.0, 0.1), (0.0, 0.2)), ("n", (0.0, 0.1), (0.0, 0.2)),      # eps_epl
+    ("n", (0.0, 0.03), (0.0, 0.06)), ("n", (0.0, 0.03), (0.0, 0.06)),  # lens centre
+    ("n", (0.0, 0.05), (0.0, 0.1)), ("n", (0.0, 0.05), (0.0, 0.1)),    # external shear
+    ("ln", (1.6, 0.15), (1.6, 0.25)),              # R_l
+    ("u", (2.0, 6.0), (0.5, 8.0)),                 # n_l
+    ("tn", (0.0, 0.05, -0.15, 0.15), (0.0, 0.1, -0.15, 0.15)),
+    ("tn", (0.0, 0.05, -0.15, 0.15), (0.0, 0.1, -0.15, 0.15)),         # eps_l
+    ("n", (0.0, 0.01), (0.0, 0.02)), ("n", (0.0, 0.01), (0.0, 0.02)),  # lens light centre
+    ("ln", (300.0, 0.3), (300.0, 0.5)),            # I_l
+    ("ln", (0.25, 0.15), (0.25, 0.25)),            # R_s
+    ("u", (0.5, 4.0), (0.5, 8.0)),                 # n_s
+    ("tn", (0.0, 0.15, -0.5, 0.5), (0.0, 0.3, -0.5, 0.5)),
+    ("tn", (0.0, 0.15, -0.5, 0.5), (0.0, 0.3, -0.5, 0.5)),             # eps_s
+    ("n", (0.0, 0.25), (0.0, 0.5)), ("n", (0.0, 0.25), (0.0, 0.5)),    # source centre
+    ("ln", (150.0, 0.5), (150.0, 0.9)),            # I_s
+]
+
+
+PAPER_AMP_INDEX = (14, 21)
+
+
+def _paper_median(i, median, pix):
+    return median * pix * pix if i in PAPER_AMP_INDEX else median
+
+
+def paper_sim_params(rng: np.random.Generator, size: int, pix: float = PIX) -> np.ndarray:
+    """Draws from the paper's simulation distribution (eq. sim-dist), [size, 22]."""
+    cols = []
+    for i, (fam, a, _) in enumerate(PAPER_DIST):
+        if fam == "ln":
+            cols.append(np.exp(rng.normal(np.log(_paper_median(i, a[0], pix)), a[1], size)))
+        elif fam == "tn":
+            cols.append(_trunc_normal(rng, a[0], a[1], a[2], a[3], size))
+        elif fam == "n":
+            cols.append(rng.normal(a[0], a[1], size))
+        else:
+            cols.append(rng.uniform(a[0], a[1], size))
+    return np.stack(cols, axis=1).astype(np.float32)
 
 
 def spec_custom(N: int, k: int, epl: bool, lens_light: bool, nmax: int, K: int = 21,
@@ -202,6 +263,8 @@ def param_spread(spec: Spec) -> np.ndarray:
 
 
 def draw_truth(spec: Spec, seed: int) -> np.ndarray:
+    if spec.dist == "paper":
+        return paper_sim_params(np.random.default_rng(seed), 1, spec.pix)[0]
     return draw_params(spec, np.random.default_rng(seed), 1)[0]
 
 
@@ -252,6 +315,14 @@ def fit_priors(spec: Spec) -> list:
     def U(lo, hi):
         return {"family": UNIFORM, "mu": 0.0, "sigma": 1.0, "lo": lo, "hi": hi}
 
+    if spec.dist == "paper":  # the prior of eq. sim-dist
+        out = []
+        for i, (f, _, b) in enumerate(PAPER_DIST):
+            if f == "ln":
+                out.append(LN(_paper_median(i, b[0], spec.pix), b[1]))
+            else:
+                out.append({"tn": TN, "n": N, "u": U}[f](*b))
+        return [dict(p) for p in out]
     pr = [LN(1.25, 0.4)] + ([TN(2.0, 0.5, 1.0, 3.0)] if spec.epl else [])
     pr += [N(0, 0.2), N(0, 0.2), N(0, 0.1), N(0, 0.1)]
     if spec.shear:

@@ -39,4 +39,5 @@ if __name__ == "__main__":
     make(synth.spec_c1(), 0)
     for s in range(5):
         make(synth.spec_c2(), s)
+    make(synth.spec_paper80(), 6)  # arc signal-to-noise 106, the paper's typical ~100
     print("ok")
