@@ -164,6 +164,7 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
         "hmc_step_size": info["step_size"],
         "rhat_max": round(float(np.max(rhat)), 4),
         "ess_min": round(float(np.min(ess)), 1),
+        "ess_per_s_hmc": round(float(np.min(ess)) / (t3 - t2), 1),
         "truth_pull_median": round(float(np.median(pull)), 3),
         "truth_pull_max": round(float(np.max(pull)), 3),
         "paper_context": "Table 1: 17 s + 52 s + 36 s = 105 s on 4x A100 (about 6 min on one) "
@@ -283,6 +284,17 @@ def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16):
     }
 
 
+def _finite(x):
+    """JSON has no inf / nan: non-finite numbers are written as null."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,7 +403,7 @@ def main():
         out["pipeline_epl60"] = dict(workload="epl60", **pipeline_bench(spec, *stored(spec)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

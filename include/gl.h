@@ -3,7 +3,8 @@
  *
  * Batched GIGA-Lens forward model, Gaussian log-likelihood and its gradient, evaluated for
  * many parameter vectors at once on one GPU (Gu et al. 2022, arXiv:2202.07663), plus a
- * fixed-budget multi-start fit and a continuous-batching server for streams of systems.
+ * fixed-budget multi-start fit, variational inference, preconditioned HMC, and a
+ * continuous-batching server for streams of systems.
  *
  * Conventions shared by every entry point
  *   - Return value: GL_OK (0) on success, GL_PENDING (1) from gl_poll only, a negative
