@@ -200,9 +200,12 @@ GL_HD void decode_lights(const float* th, int mass, int shear, int lens_light, i
 // finite, positive arguments). Written from the mathematics:
 //   rcp: hardware estimate refined by two Newton steps r <- r (2 - x r);
 //   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m-1)/(m+1),
-//        |s| <= 0.172, summed to s^15 (relative error < 1e-15);
+//        |s| <= 0.172, summed to s^11 (absolute truncation < 2e-11);
 //   exp: x = k ln2 + r with |r| <= ln2/2 (Cody-Waite reduction, ln2 as a double plus its
-//        tail), e^r by its Taylor series to r^12 (truncation < 2e-16), then scaled by 2^k.
+//        tail), e^r by its Taylor series to r^10 (relative truncation < 3e-13), then scaled
+//        by 2^k.
+// The targets sit below the 1e-10 relative tolerance of the deflection series: the ray
+// trace needs |alpha| to ~1e-9 arcsec, far below FP32 resolution but far above FP64's.
 // ------------------------------------------------------------------------------------------
 constexpr double kLn2 = 0.6931471805599453;        // nearest double to ln 2
 constexpr double kLn2Tail = 2.3190468138462996e-17;  // ln 2 - kLn2
@@ -235,9 +238,7 @@ GL_HD double log_f64(double x) {
   }
   const double s = (m - 1.0) * rcp_f64(m + 1.0);
   const double s2 = s * s;
-  double p = 1.0 / 15.0;
-  p = fma(p, s2, 1.0 / 13.0);
-  p = fma(p, s2, 1.0 / 11.0);
+  double p = 1.0 / 11.0;
   p = fma(p, s2, 1.0 / 9.0);
   p = fma(p, s2, 1.0 / 7.0);
   p = fma(p, s2, 1.0 / 5.0);
@@ -250,9 +251,7 @@ GL_HD double log_f64(double x) {
 GL_HD double exp_f64(double x) {
   const double k = rint(x * kInvLn2);
   const double r = fma(-k, kLn2Tail, fma(-k, kLn2, x));
-  double p = 1.0 / 479001600.0;  // 1/12!
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
+  double p = 1.0 / 3628800.0;  // 1/10!
   p = fma(p, r, 1.0 / 362880.0);
   p = fma(p, r, 1.0 / 40320.0);
   p = fma(p, r, 1.0 / 5040.0);
@@ -339,7 +338,10 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     // nterms_d terms only.
     double sr = 0.0, si = 0.0;
     const int nt4 = (c.nterms + 3) & ~3;
-    const int nd4 = ADJ ? ((c.nterms_d + 3) & ~3) : 0;
+    // dS/dX: by its series only for small |eps|; otherwise from S below. dS/dt (EPL): always
+    // by its series.
+    const bool sx_series = ADJ && c.epsabs < kSxClosedMin;
+    const int nd4 = (ADJ && (MASS == 1 || sx_series)) ? ((c.nterms_d + 3) & ~3) : 0;
     for (int n0 = nt4 - 4; n0 >= nd4; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
@@ -351,22 +353,49 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     if (ADJ) {
       const float yrf = float(yr), yif = float(yi);
       float dr = 0.f, di = 0.f, tr = 0.f, ti = 0.f;
-      for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+      if (sx_series) {
+        for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
-        for (int q = 3; q >= 0; --q) {
-          const int n = n0 + q;
-          const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
-          si = fma(sr, yi, si * yr);
-          sr = nsr;
-          const float ndr = fmaf(dr, yrf, fmaf(-di, yif, ncs[n]));
-          di = fmaf(dr, yif, di * yrf);
-          dr = ndr;
-          if (MASS == 1) {
+          for (int q = 3; q >= 0; --q) {
+            const int n = n0 + q;
+            const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
+            si = fma(sr, yi, si * yr);
+            sr = nsr;
+            const float ndr = fmaf(dr, yrf, fmaf(-di, yif, ncs[n]));
+            di = fmaf(dr, yif, di * yrf);
+            dr = ndr;
+            if (MASS == 1) {
+              const float ntr = fmaf(tr, yrf, fmaf(-ti, yif, dcs[n]));
+              ti = fmaf(tr, yif, ti * yrf);
+              tr = ntr;
+            }
+          }
+        }
+      } else {
+        for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+          for (int q = 3; q >= 0; --q) {
+            const int n = n0 + q;
+            const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
+            si = fma(sr, yi, si * yr);
+            sr = nsr;
             const float ntr = fmaf(tr, yrf, fmaf(-ti, yif, dcs[n]));
             ti = fmaf(tr, yif, ti * yrf);
             tr = ntr;
           }
         }
+        // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
+        //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S,
+        // (as series: the coefficient of (-X)^n on both sides agrees for every n). The
+        // numerator cancels like |X| = |eps|, so it is formed in FP64 from the FP64 S.
+        const double h = 0.5 * c.t;
+        const double xsr = Xr * sr - Xi * si, xsi = Xr * si + Xi * sr;
+        const float numr = float((1.0 - h) * (1.0 - sr) - h * xsr);
+        const float numi = float(-(1.0 - h) * si - h * xsi);
+        const float denr = float(Xr + Xr * Xr - Xi * Xi), deni = float(Xi + 2.0 * Xr * Xi);
+        const float inv = rcp_f32(denr * denr + deni * deni);
+        dr = -(numr * denr + numi * deni) * inv;  // dS/dy = -dS/dX
+        di = -(numi * denr - numr * deni) * inv;
       }
       m.SX = {-dr, -di};  // d/dX = -d/dy
       m.St = {tr, ti};
@@ -497,13 +526,15 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
   float hu[NMAX + 1], hv[NMAX + 1];
   hermite<NMAX>(u, hu);
   hermite<NMAX>(v, hv);
+  // h_0 = 1: every sum starts from its n = 0 term (no addition of a zero, which the
+  // compiler must keep for signed zeros)
   float U = 0.f;
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1) {
-    float T = 0.f;
+    float T = c.shp[shp_index(n1, 0)];
 #pragma unroll
-    for (int n2 = 0; n2 <= NMAX - n1; ++n2) T = fmaf(c.shp[shp_index(n1, n2)], hv[n2], T);
-    U = fmaf(hu[n1], T, U);
+    for (int n2 = 1; n2 <= NMAX - n1; ++n2) T = fmaf(c.shp[shp_index(n1, n2)], hv[n2], T);
+    U = n1 == 0 ? T : fmaf(hu[n1], T, U);
   }
   return exp2_f32(-0.5f * kLog2e * (u * u + v * v)) * U;
 }
@@ -524,19 +555,20 @@ GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float*
   hermite<NMAX>(v, hv);
   const float G = exp2_f32(-0.5f * kLog2e * (u * u + v * v));
   const float sg = sb * G;
+  // h_0 = 1: sums start from their first term (see shapelet_fwd)
   float U = 0.f, Uu = 0.f, Uv = 0.f;
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1) {
-    float T = 0.f, Tv = 0.f;
+    float T = c.shp[shp_index(n1, 0)], Tv = 0.f;
 #pragma unroll
-    for (int n2 = 0; n2 <= NMAX - n1; ++n2) {
+    for (int n2 = 1; n2 <= NMAX - n1; ++n2) {
       const float ck = c.shp[shp_index(n1, n2)];
       T = fmaf(ck, hv[n2], T);
-      if (n2 > 0) Tv = fmaf(ck, sqrtf(2.0f * n2) * hv[n2 - 1], Tv);
+      Tv = n2 == 1 ? ck * 1.41421356237f : fmaf(ck, sqrtf(2.0f * n2) * hv[n2 - 1], Tv);
     }
-    U = fmaf(hu[n1], T, U);
-    Uv = fmaf(hu[n1], Tv, Uv);
-    if (n1 > 0) Uu = fmaf(sqrtf(2.0f * n1) * hu[n1 - 1], T, Uu);
+    U = n1 == 0 ? T : fmaf(hu[n1], T, U);
+    if (n1 < NMAX) Uv = n1 == 0 ? Tv : fmaf(hu[n1], Tv, Uv);
+    if (n1 > 0) Uu = n1 == 1 ? 1.41421356237f * T : fmaf(sqrtf(2.0f * n1) * hu[n1 - 1], T, Uu);
   }
   float hvs[NMAX + 1];
 #pragma unroll

@@ -16,6 +16,9 @@ constexpr float kLightEpsMax = 0.9f;
 constexpr float kSieClosedMin = 0.1f;  // SIE closed form for |eps| >= this, series below
 constexpr double kSeriesTol = 1e-10;   // EPL series truncation, relative (far below FP32)
 constexpr double kSeriesTolDeriv = 1e-7;  // truncation of the derivative series (adjoint)
+// dS/dX from S by the first-order identity of the series for |eps| >= this (its cancellation
+// costs 1e-10 / |eps| relative: below 1e-8 here); the derivative series below
+constexpr double kSxClosedMin = 0.02;
 
 // Accumulator slots of the adjoint (per particle, summed over sub-pixels).
 enum AccSlot {

@@ -143,11 +143,13 @@ def test_ragged_configs(glens, case):
     assert err.max() < 2e-5, err.max()
 
 
-@pytest.mark.parametrize("eps", [0.0005, 0.05, 0.0999, 0.1001, 0.3, 0.55, 0.7])
+@pytest.mark.parametrize("eps", [0.0005, 0.0199, 0.0201, 0.05, 0.0999, 0.1001, 0.3, 0.55, 0.7])
 @pytest.mark.parametrize("epl", [False, True])
 def test_mass_ellipticity_range(glens, eps, epl):
-    """Both SIE branches (series below |eps| = 0.1, closed form above), the EPL series up to
-    its longest expansion, and the |eps| clamp at 0.6."""
+    """Both SIE branches (series below |eps| = 0.1, closed form above), both ways of getting
+    the series derivative dS/dX in the adjoint (its own series below |eps| = 0.02, the
+    first-order identity above), the EPL series up to its longest expansion, and the |eps|
+    clamp at 0.6."""
     spec = synth.Spec("e", 32, 32, 2, epl=epl, lens_light=False, nmax=2,
                       psf=synth.moffat_psf(7, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
     truth = synth.draw_truth(spec, 11)
