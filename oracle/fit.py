@@ -151,3 +151,43 @@ def adam_step(z, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1 - beta1 ** t)
     vhat = v / (1 - beta2 ** t)
     return z - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def draw_starts(priors, seed, P):
+    """The P multi-start points in unconstrained space (Sec. 2.3: starts drawn from the
+    prior), from the counter-based generator of oracle.rng with counter
+    (particle, parameter, 0x6c656e73, 0): u1, u2 from the two word pairs; normal and
+    log-normal priors take the Box-Muller normal, truncated normals the inverse CDF at
+    Phi(a) + u1 (Phi(b) - Phi(a)), uniforms u1; bounded families map through the logit of
+    the position within (lo, hi) clipped to [1e-7, 1 - 1e-7]. Prior parameters are used at
+    float32, the precision the library stores them in; the result is rounded to float32."""
+    from scipy.special import erfinv
+    from . import rng
+    d = len(priors)
+    p_idx = np.arange(P, dtype=np.uint64)[:, None]
+    j_idx = np.arange(d, dtype=np.uint64)[None, :]
+    ctr = np.stack(np.broadcast_arrays(p_idx, j_idx, np.uint64(0x6C656E73), np.uint64(0)), axis=-1)
+    w = rng.philox4x32_10(ctr, rng.split_seed(seed))
+    u1, u2 = rng.u01(w[..., 0], w[..., 1]), rng.u01(w[..., 2], w[..., 3])
+    out = np.empty((P, d))
+    f32 = lambda x: float(np.float32(x))
+    for j, pr in enumerate(priors):
+        fam = pr["family"]
+        mu, sg = f32(pr.get("mu", 0.0)), f32(pr.get("sigma", 1.0))
+        lo, hi = f32(pr.get("lo", 0.0)), f32(pr.get("hi", 0.0))
+        if fam in (NORMAL, LOGNORMAL):
+            n = np.sqrt(-2.0 * np.log(u1[:, j])) * np.cos(2.0 * np.pi * u2[:, j])
+            out[:, j] = mu + sg * n
+            continue
+        if fam == TRUNCNORMAL:
+            # the standardised bounds in float32 arithmetic, as the library forms them
+            za = float((np.float32(lo) - np.float32(mu)) / np.float32(sg))
+            zb = float((np.float32(hi) - np.float32(mu)) / np.float32(sg))
+            a, b = _std_normal_cdf(za), _std_normal_cdf(zb)
+            x = mu + sg * math.sqrt(2.0) * erfinv(2.0 * (a + u1[:, j] * (b - a)) - 1.0)
+            u = (x - lo) / (hi - lo)
+        else:
+            u = u1[:, j]
+        u = np.clip(u, 1e-7, 1.0 - 1e-7)
+        out[:, j] = np.log(u) - np.log1p(-u)
+    return out.astype(np.float32)

@@ -115,6 +115,21 @@ def test_starts_follow_the_prior(G):
     assert not np.array_equal(st3.store()[0].cpu().numpy(), z.astype(np.float32))
 
 
+@pytest.mark.parametrize("spec_fn", [synth.spec_c2, synth.spec_paper80])
+def test_starts_match_the_oracle_generator(G, spec_fn):
+    """The starts are the oracle's own draws (its Philox4x32-10 from the published
+    definition, the same transforms): every family, to float32 rounding."""
+    spec = spec_fn()
+    obs = np.zeros((spec.H, spec.W), np.float32)
+    priors = synth.fit_priors(spec)
+    model = G.Model.from_spec(spec, obs)
+    st = G.FitState(model, 3000, 10, priors, seed=0x1234_5678_9ABC)
+    z = st.store()[0].cpu().numpy()
+    z_ref = ofit.draw_starts(priors, 0x1234_5678_9ABC, 3000)
+    np.testing.assert_allclose(z, z_ref, rtol=1e-6, atol=1e-6)
+    _say("identical fraction", np.mean(z == z_ref))
+
+
 def test_fit_result_matches_oracle_at_the_best_particle(G):
     spec = synth.spec_c1()
     obs, truth = load_workload(spec.name)

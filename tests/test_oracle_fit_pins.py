@@ -125,3 +125,18 @@ def prior_list_for(spec):
     sim-dist where it lists them)."""
     from synth import fit_priors
     return fit_priors(spec)
+
+
+def test_draw_starts_follow_the_prior():
+    """Sec. 2.3: starts are draws from the prior. The oracle's draws (its own Philox and
+    transforms) pass Kolmogorov-Smirnov tests against scipy's distributions for every
+    family, and depend only on (seed, particle, parameter)."""
+    z = fit.draw_starts(PRIORS, 99, 20000).astype(np.float64)
+    th = fit.bijector(z, PRIORS)
+    cdfs = [stats.norm(0.1, 0.2).cdf, stats.lognorm(s=0.4, scale=1.25).cdf,
+            stats.truncnorm((1 - 2) / 0.5, (3 - 2) / 0.5, loc=2, scale=0.5).cdf,
+            stats.uniform(0.5, 7.5).cdf]
+    for j, cdf in enumerate(cdfs):
+        assert stats.kstest(th[:, j], cdf).pvalue > 1e-3, j
+    np.testing.assert_array_equal(fit.draw_starts(PRIORS, 99, 50), z[:50].astype(np.float32))
+    assert not np.array_equal(fit.draw_starts(PRIORS, 98, 50), z[:50].astype(np.float32))
