@@ -143,8 +143,9 @@ int choose_tiles(int P, int HW) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit) {
-  size_t b = align256(sizeof(PConst) * P) + 2 * align256(sizeof(float) * (size_t)P * HW) +
-             align256(sizeof(double) * (size_t)P * tiles * kNAcc);
+  size_t b = align256(sizeof(PConst) * P) + 3 * align256(sizeof(float) * (size_t)P * HW) +
+             align256(sizeof(double) * (size_t)P * tiles * kNAcc) +
+             align256(sizeof(double) * (size_t)P * kConvMaxBands * 2);
   if (fit) b += align256(sizeof(double) * P) + 2 * align256(sizeof(float) * (size_t)P * d);
   return b;
 }
@@ -175,6 +176,8 @@ int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit) 
   ws.m0 = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
   ws.sbar = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
   ws.acc = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * cT * kNAcc));
+  ws.seed = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
+  ws.lpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * kConvMaxBands * 2));
   if (fit) {
     ws.logl = reinterpret_cast<double*>(take(sizeof(double) * cP));
     ws.grad = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
@@ -218,7 +221,20 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.m0 = ws.m0;
   s.sbar = ws.sbar;
   s.acc = ws.acc;
+  s.seed = ws.seed;
+  s.lpart = ws.lpart;
+  conv_bands(P, c.H, &s.bands, &s.band_rows);
   return s;
+}
+
+void conv_bands(int P, int H, int* bands, int* band_rows) {
+  // aim at >= 512 workgroups in the PSF pass; bands of whole strips, at most kConvMaxBands
+  const int nstrip = (H + kConvRows - 1) / kConvRows;
+  const int want = P >= 512 ? 1 : (512 + std::max(P, 1) - 1) / std::max(P, 1);
+  const int b = std::max(1, std::min({want, nstrip, kConvMaxBands}));
+  const int spb = (nstrip + b - 1) / b;  // strip rows per band
+  *band_rows = spb * kConvRows;
+  *bands = (H + *band_rows - 1) / *band_rows;
 }
 
 int subpix_key(const ModelCfg& c) { return c.mass * 16 + (c.nmax + 1); }
@@ -257,9 +273,19 @@ template <int... I>
 static void fill_conv(GroupKernel* f, std::integer_sequence<int, I...>) {
   ((f[I] = conv_kernel<2 * I + 1>), ...);
 }
+template <int... I>
+static void fill_conv_band(GroupKernel* f, GroupKernel* fa, std::integer_sequence<int, I...>) {
+  ((f[I] = conv_band_kernel<2 * I + 1>), ...);
+  ((fa[I] = conv_band_adj_kernel<2 * I + 1>), ...);
+}
 struct ConvTable {
   GroupKernel k[(GL_MAX_PSF + 1) / 2] = {};
-  ConvTable() { fill_conv(k, std::make_integer_sequence<int, (GL_MAX_PSF + 1) / 2>{}); }
+  GroupKernel band[(GL_MAX_PSF + 1) / 2] = {};
+  GroupKernel band_adj[(GL_MAX_PSF + 1) / 2] = {};
+  ConvTable() {
+    fill_conv(k, std::make_integer_sequence<int, (GL_MAX_PSF + 1) / 2>{});
+    fill_conv_band(band, band_adj, std::make_integer_sequence<int, (GL_MAX_PSF + 1) / 2>{});
+  }
 };
 static const ConvTable& conv_table() {
   static ConvTable t;
@@ -294,25 +320,37 @@ size_t conv_lds_bytes(int H, int W, int K, int mode) {
   return sizeof(float) * np;
 }
 
+// Raise the dynamic LDS limit of the PSF kernels once; fails only if `lds` needs it.
+static int conv_lds_limit(size_t lds) {
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    const ConvTable& t = conv_table();
+    for (const GroupKernel* tab : {t.k, t.band, t.band_adj})
+      for (int i = 0; i < (GL_MAX_PSF + 1) / 2; ++i) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tab[i]),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 256);
+        if (e != hipSuccess) attr_err = e;
+      }
+  });
+  if (attr_err != hipSuccess && lds > 64 * 1024)
+    return set_error(GL_E_DEVICE, "cannot raise the LDS limit: %s", hipGetErrorString(attr_err));
+  return GL_OK;
+}
+
 int launch_conv(int K, const Group& g, size_t lds, hipStream_t st) {
   for (int i = 0; i < g.nsys; ++i) {
     const int nstrip = (g.sys[i].H + kConvRows - 1) / kConvRows;
     if (nstrip * g.sys[i].W > kConvMaxStrips * kConvThreads)
       return set_error(GL_E_UNIMPLEMENTED, "image too large for the PSF kernel");
   }
-  static std::once_flag once;
-  static hipError_t attr_err = hipSuccess;
-  std::call_once(once, [] {
-    for (auto k : conv_table().k) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
-      if (e != hipSuccess) attr_err = e;
-    }
-  });
-  if (attr_err != hipSuccess && lds > 64 * 1024)
-    return set_error(GL_E_DEVICE, "cannot raise the LDS limit: %s", hipGetErrorString(attr_err));
+  int rc = conv_lds_limit(lds);
+  if (rc) return rc;
   return launch(conv_table().k[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st);
 }
+
+
 
 // Block offsets of each system for one stage.
 template <class F>
@@ -323,6 +361,28 @@ static void set_blocks(Group& g, F per_sys) {
     b += per_sys(g.sys[i]);
   }
   g.block0[g.nsys] = b;
+}
+
+// The banded PSF pass (small batches): block offsets are set here for each kernel.
+static int launch_conv_band(int K, Group& g, int mode, hipStream_t st) {
+  size_t lds = 0;
+  for (int i = 0; i < g.nsys; ++i) {
+    const SysDesc& s = g.sys[i];
+    const int nsr = s.band_rows / kConvRows;
+    lds = std::max(lds, sizeof(float) * size_t((nsr * kConvRows + K - 1) | 1) * (s.W + K - 1));
+  }
+  int rc = conv_lds_limit(lds);
+  if (rc) return rc;
+  set_blocks(g, blocks_conv_band);
+  if ((rc = launch(conv_table().band[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st)))
+    return rc;
+  if (mode == 2)
+    return launch(conv_table().band_adj[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st);
+  if (mode == 1) {
+    set_blocks(g, [](const SysDesc& s) { return (s.P + 63) / 64; });
+    return launch(conv_band_sum_kernel, g.block0[g.nsys], 64, 0, g, st);
+  }
+  return GL_OK;
 }
 
 int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev) {
@@ -336,12 +396,18 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev
   if ((rc = launch_subpix_fwd(key, g, st))) return rc;
   GL_HIP(mark(2));
   size_t lds = 0;
+  bool banded = false;
   for (int i = 0; i < g.nsys; ++i) {
     g.sys[i].mode = mode;
     lds = std::max(lds, conv_lds_bytes(g.sys[i].H, g.sys[i].W, K, mode));
+    banded = banded || g.sys[i].bands > 1;
   }
-  set_blocks(g, blocks_conv);
-  if ((rc = launch_conv(K, g, lds, st))) return rc;
+  if (banded) {
+    if ((rc = launch_conv_band(K, g, mode, st))) return rc;
+  } else {
+    set_blocks(g, blocks_conv);
+    if ((rc = launch_conv(K, g, lds, st))) return rc;
+  }
   GL_HIP(mark(3));
   if (mode != 2) return GL_OK;
   set_blocks(g, blocks_subpix);

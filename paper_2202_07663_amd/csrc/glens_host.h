@@ -36,6 +36,8 @@ struct Workspace {
   double* logl = nullptr;  // internal log L (fits)
   float* grad = nullptr;   // internal gradient (fits)
   float* theta = nullptr;  // internal theta (fits)
+  float* seed = nullptr;   // adjoint seed of the banded PSF pass
+  double* lpart = nullptr; // per-band likelihood partial sums
   size_t bytes = 0;
 };
 size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit_buffers);
@@ -75,6 +77,9 @@ size_t conv_lds_bytes(int H, int W, int K, int mode);
 inline int blocks_prologue(const SysDesc& s) { return s.P; }  // prologue, finalize
 inline int blocks_subpix(const SysDesc& s) { return s.P * s.tiles; }
 inline int blocks_conv(const SysDesc& s) { return s.P; }
+inline int blocks_conv_band(const SysDesc& s) { return s.P * s.bands; }
+// Row bands of the PSF pass for P particles of an H-row image (1: the whole-image kernel).
+void conv_bands(int P, int H, int* bands, int* band_rows);
 
 // Run the forward (+adjoint) pipeline for a group of systems sharing key and PSF size.
 // mode: 0 image, 1 log L, 2 log L + gradient.

@@ -261,6 +261,139 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Banded PSF pass for small batches: one workgroup per (particle, band of rows), so that a
+// few particles still spread over many CUs. Band b owns output rows [b R_b, (b+1) R_b) and
+// loads the rows of its input it needs (C = (K-1)/2 more on either side). Three kernels:
+//   conv_band_kernel       the PSF, the likelihood terms (partial sums per band) and the
+//                          adjoint seed of each pixel (to a [P][H][W] buffer);
+//   conv_band_adj_kernel   the correlation of the seed with the PSF; the first band of a
+//                          particle also adds the likelihood partials (band order);
+//   conv_band_sum_kernel   the same addition when there is no adjoint pass.
+// Per pixel the arithmetic is that of conv_kernel; only the order of the log L sum differs.
+// ------------------------------------------------------------------------------------------
+struct Band {
+  int part, band, r0, r1, nsr, Hs;
+};
+
+__device__ __forceinline__ Band band_of(const SysDesc& s, int local, int K) {
+  Band b;
+  b.part = local / s.bands;
+  b.band = local - b.part * s.bands;
+  b.r0 = b.band * s.band_rows;
+  b.r1 = min(s.H, b.r0 + s.band_rows);
+  b.nsr = (b.r1 - b.r0 + kConvRows - 1) / kConvRows;
+  b.Hs = (b.nsr * kConvRows + K - 1) | 1;
+  return b;
+}
+
+// Rows [r0 - C, r1 + C) of src (zero outside the image) into the column-major LDS tile.
+template <int K>
+__device__ __forceinline__ void load_band(const float* __restrict__ src, const SysDesc& s,
+                                          const Band& b, float* A) {
+  constexpr int C = (K - 1) / 2;
+  const int W = s.W, Wp = W + K - 1;
+  for (int idx = threadIdx.x; idx < b.Hs * Wp; idx += blockDim.x) A[idx] = 0.f;
+  __syncthreads();
+  const int lo = max(0, b.r0 - C), hi = min(s.H, b.r1 + C);
+  for (int idx = threadIdx.x; idx < (hi - lo) * W; idx += blockDim.x) {
+    const int i = lo + idx / W, j = idx - (idx / W) * W;
+    A[(j + C) * b.Hs + (i - b.r0) + C] = src[(size_t)i * W + j];
+  }
+  __syncthreads();
+}
+
+template <int K>
+__global__ void __launch_bounds__(kConvThreads) conv_band_kernel(Group g) {
+  extern __shared__ float lds[];
+  __shared__ double red[kConvThreads / 64];
+  const int si = find_sys(g, blockIdx.x);
+  const SysDesc& s = g.sys[si];
+  const Band b = band_of(s, blockIdx.x - g.block0[si], K);
+  constexpr int R = kConvRows;
+  const int W = s.W, HW = s.H * W, mode = s.mode;
+  load_band<K>(s.m0 + (size_t)b.part * HW, s, b, lds);
+  double ll = 0.0, c2 = 0.0;
+  for (int sidx = threadIdx.x; sidx < b.nsr * W; sidx += blockDim.x) {
+    const int st = sidx / W, j = sidx - st * W, i0 = st * R;
+    float acc[R];
+    correlate_strip<K>(lds, b.Hs, i0, j, s.psf_flip, acc);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = b.r0 + i0 + r;
+      if (i >= b.r1) break;
+      const float m = acc[r];
+      const size_t o = (size_t)b.part * HW + i * W + j;
+      if (mode == 0) {
+        s.img[o] = m;
+        continue;
+      }
+      const float pos = m > 0.f ? m : 0.f;
+      const float s2 = s.s2b + pos * s.inv_gt;
+      const float res = s.obs[i * W + j] - m;
+      const float is2 = rcp_f32(s2);
+      const float chi = res * res * is2;
+      c2 += double(chi);
+      ll += double(chi + kLn2f * log2_f32(6.283185307179586f * s2));
+      if (mode == 2) {
+        const float sp = m > 0.f ? s.inv_gt : 0.f;
+        s.seed[o] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
+      }
+    }
+  }
+  if (mode == 0) return;
+  const double tot = block_sum(ll, red);
+  const double ctot = block_sum(c2, red);
+  if (threadIdx.x == 0) {
+    double* lp = s.lpart + ((size_t)b.part * kConvMaxBands + b.band) * 2;
+    lp[0] = tot;
+    lp[1] = ctot;
+  }
+}
+
+// log L and chi^2 of one particle from its bands' partial sums.
+__device__ __forceinline__ void band_totals(const SysDesc& s, int part) {
+  const double* lp = s.lpart + (size_t)part * kConvMaxBands * 2;
+  double tot = 0.0, ctot = 0.0;
+  for (int q = 0; q < s.bands; ++q) {
+    tot += lp[2 * q];
+    ctot += lp[2 * q + 1];
+  }
+  const double v = -0.5 * tot;
+  s.logl[part] = isfinite(v) ? v : -INFINITY;
+  if (s.chi2) s.chi2[part] = ctot;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kConvThreads) conv_band_adj_kernel(Group g) {
+  extern __shared__ float lds[];
+  const int si = find_sys(g, blockIdx.x);
+  const SysDesc& s = g.sys[si];
+  const Band b = band_of(s, blockIdx.x - g.block0[si], K);
+  constexpr int R = kConvRows;
+  const int W = s.W, HW = s.H * W;
+  if (b.band == 0 && threadIdx.x == 0) band_totals(s, b.part);
+  load_band<K>(s.seed + (size_t)b.part * HW, s, b, lds);
+  for (int sidx = threadIdx.x; sidx < b.nsr * W; sidx += blockDim.x) {
+    const int st = sidx / W, j = sidx - st * W, i0 = st * R;
+    float acc[R];
+    correlate_strip<K>(lds, b.Hs, i0, j, s.psf, acc);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = b.r0 + i0 + r;
+      if (i >= b.r1) break;
+      s.sbar[(size_t)b.part * HW + i * W + j] = acc[r] * s.inv_k2;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) conv_band_sum_kernel(Group g) {
+  const int si = find_sys(g, blockIdx.x);
+  const SysDesc& s = g.sys[si];
+  const int p = (blockIdx.x - g.block0[si]) * blockDim.x + threadIdx.x;
+  if (p < s.P) band_totals(s, p);
+}
+
+// ------------------------------------------------------------------------------------------
 // sub-pixel adjoint
 // ------------------------------------------------------------------------------------------
 template <int NMAX>

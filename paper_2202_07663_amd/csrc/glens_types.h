@@ -99,6 +99,8 @@ struct SysDesc {
   int tiles;           // sub-pixel work tiles per particle
   int pix_per_tile;
   int mode;            // conv kernel: 0 image, 1 log L, 2 log L + adjoint seed
+  int bands;           // banded PSF pass: row bands per particle (1: whole image)
+  int band_rows;       // rows per band (a multiple of the strip height)
   const float* obs;
   const float* psf;      // K*K
   const float* psf_flip; // K*K, flipped in both axes
@@ -120,9 +122,12 @@ struct SysDesc {
   double* acc;           // [P][tiles][kNAcc]
   double* logl;          // [P]
   float* grad;           // [P][d]
+  float* seed;           // [P][H][W] adjoint seed (banded PSF pass)
+  double* lpart;         // [P][max bands][2] log L and chi^2 partial sums per band
 };
 
 constexpr int kMaxGroup = 10;
+constexpr int kConvMaxBands = 8;  // row bands per particle in the small-batch PSF pass
 
 // Systems that share one launch (same kernel configuration). Passed by value.
 struct Group {
