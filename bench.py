@@ -109,8 +109,9 @@ def workload():
 # The modelling pipeline of one system (Table 1): multi-start Adam (n_MAP starts x K_MAP
 # steps, lr 1e-2 -> 1e-3 linear), VI (n_VI samples x K_VI iterations, lr 0 -> 1e-3
 # quadratic over 500, Sigma_1 = 1e-6 I, from the best start), then HMC (chains drawn from the
-# VI surrogate, 250 burn-in + 750 recorded trajectories of L leapfrog steps, eps_0 = 0.3
-# adapted to acceptance 0.75 over 80% of burn-in, M^-1 = the VI covariance). Every stage
+# VI surrogate, 250 burn-in + 750 recorded trajectories starting at L leapfrog steps of
+# eps_0 = 0.3, with the step size (acceptance 0.75) and the trajectory length (ChEES, at most
+# 100 steps) adapted over 80% of burn-in, M^-1 = the VI covariance). Every stage
 # runs on the GPU; each is timed from its first launch to a device sync. Two workloads:
 #   paper80: the paper's simulated-system setting (eq. sim-dist truth and prior, 80x80,
 #            k = 2, sigma_bkg 0.2, t_exp 100 s; truth seed 6, whose arcs have the typical
@@ -121,7 +122,7 @@ def workload():
 # ------------------------------------------------------------------------------------------
 
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
-                   chains=64, L=10, n_burn=250, n_samples=750):
+                   chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100):
     import torch
     import synth
     import paper_2202_07663_amd as G
@@ -140,7 +141,7 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     chol = got["chol"].cpu().numpy()
     t2 = time.perf_counter()
     h = G.HMC(model, chains, L, n_burn, n_samples, priors, step_size=0.3, seed=seed + 3,
-              z0=z0, mass_chol=chol)
+              z0=z0, mass_chol=chol, adapt_length=True, max_leapfrog=max_leapfrog)
     h.run()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -150,7 +151,8 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     mean, sd = flat.mean(axis=0), flat.std(axis=0)
     pull = np.abs(mean - truth) / np.maximum(sd, 1e-30)
     rhat, ess = dg.split_rhat(th), dg.ess(th)
-    grad_evals = n_map * k_map + n_vi * k_vi + chains * (n_burn + n_samples) * L
+    grad_evals = n_map * k_map + n_vi * k_vi + round(chains * (n_burn + n_samples) *
+                                                     info["mean_leapfrog"])
     return {
         "config": {"map": [n_map, k_map], "vi": [n_vi, k_vi],
                    "hmc": {"chains": chains, "L": L, "burn": n_burn, "samples": n_samples}},
@@ -158,7 +160,10 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
                     "total": round(t3 - t0, 3)},
         "grad_evals": grad_evals,
         "grad_evals_per_s": round(grad_evals / (t3 - t0), 1),
-        "hmc_us_per_leapfrog": round(1e6 * (t3 - t2) / ((n_burn + n_samples) * L), 2),
+        "hmc_us_per_leapfrog": round(1e6 * (t3 - t2) / ((n_burn + n_samples) *
+                                                        info["mean_leapfrog"]), 2),
+        "hmc_trajectory_length": round(info["trajectory_length"], 4),
+        "hmc_mean_leapfrog": round(info["mean_leapfrog"], 2),
         "map_chi2nu": round(r["chi2nu"], 4),
         "hmc_accept": round(info["accept_mean"], 4),
         "hmc_step_size": info["step_size"],

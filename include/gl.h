@@ -245,6 +245,14 @@ int gl_vi_set_state(gl_vi* v, const double* x, const double* m, const double* s,
  * follows dual averaging (Hoffman & Gelman 2014, gamma 0.05, t0 10, kappa 0.75,
  * mu = log(10 step_size)) of the chain-mean acceptance probability towards target_accept
  * (the paper: 0.75 over the first 80% of burn-in); it then stays at the averaged value.
+ * With adapt_length the trajectory length T (initially n_leapfrog step_size) adapts too, as
+ * in Hoffman, Radul & Sountsov (2021, ChEES): trajectory k runs L = ceil(u_k T / eps)
+ * leapfrog steps (at most max_leapfrog) with u_k the k-th van der Corput number (base 2),
+ * shared by all chains, and during the same adaptation window log T takes Adam steps
+ * (beta1 0, beta2 0.95, rate 0.025) up the acceptance-weighted estimate of d ChEES / d log T,
+ * ChEES = E[(|z' - E z'|^2 - |z - E z|^2)^2] / 4, whose per-chain term is
+ * (|z' - zbar'|^2 - |z - zbar|^2) ((z' - zbar') . M^-1 p') u T (means over chains); T is then
+ * fixed at its average with weights m^-0.75. The paper adapts both as in these references.
  * Every chain is one particle of the likelihood pipeline: a leapfrog step is one batched
  * gradient launch over all chains. Random numbers: Philox4x32-10 keyed by `seed`, counter
  * (chain, parameter, trajectory, purpose).
@@ -260,6 +268,8 @@ typedef struct gl_hmc_opts {
   float adapt_frac;            /* share of burn-in with step-size adaptation, in [0, 1] */
   uint64_t seed;
   const float* inv_mass;       /* host, copied: M^-1, NULL for the identity; see form */
+  int adapt_length;            /* 1: also adapt the trajectory length (see above) */
+  int max_leapfrog;            /* cap on leapfrog steps per trajectory (0: 1000) */
   int inv_mass_form;           /* GL_MASS_DIAG: inv_mass is the diagonal [d] (> 0);
                                   GL_MASS_DENSE: the full symmetric positive definite [d][d]
                                   row-major (e.g. a posterior covariance of z);
@@ -272,6 +282,8 @@ typedef struct gl_hmc_info {
   float step_size;       /* current eps (the averaged one once adaptation ended) */
   double accept_mean;    /* mean acceptance probability over the recorded trajectories */
   int trajectories;      /* trajectories run so far */
+  float trajectory_length; /* T (adapted), or n_leapfrog eps without length adaptation */
+  double mean_leapfrog;  /* mean leapfrog steps per trajectory so far */
 } gl_hmc_info;
 
 typedef struct gl_hmc gl_hmc;

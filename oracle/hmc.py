@@ -123,3 +123,84 @@ def lens_objective(model, obs, priors):
         f, g, _ = objective_and_grad(model, zz, obs, priors)
         return f, g
     return fg
+
+
+# ------------------------------------------------------------------------------------------
+# Trajectory-length adaptation (Hoffman, Radul & Sountsov 2021, "An adaptive MCMC scheme
+# for setting trajectory lengths in Hamiltonian Monte Carlo"): the length T of every
+# trajectory is jittered, t = u T with u from a low-discrepancy sequence shared by all chains,
+# and log T follows stochastic gradient ascent on the ChEES criterion
+#   ChEES(T) = E[(|z' - E z'|^2 - |z - E z|^2)^2] / 4
+# (change in the expected squared jump distance), whose gradient estimate per chain i is
+#   g_i = (|z'_i - zbar'|^2 - |z_i - zbar|^2) ((z'_i - zbar') . M^-1 p'_i) u,
+# averaged over chains with the acceptance probabilities as weights; means are over chains.
+# ------------------------------------------------------------------------------------------
+
+def halton(k, base=2):
+    """The k-th (k >= 1) element of the van der Corput sequence in the given base."""
+    f, r = 1.0, 0.0
+    while k > 0:
+        f /= base
+        r += f * (k % base)
+        k //= base
+    return r
+
+
+def chees_gradient(z0, z1, p1, inv_mass, accept, u):
+    """Acceptance-weighted ChEES gradient estimate w.r.t. T from the chains' starts z0,
+    proposals z1 and end momenta p1 (rows are chains)."""
+    z0, z1 = np.asarray(z0, np.float64), np.asarray(z1, np.float64)
+    c0, c1 = z0 - z0.mean(axis=0), z1 - z1.mean(axis=0)
+    v1 = _apply_inv_mass(inv_mass, np.asarray(p1, np.float64))
+    diff = np.sum(c1 * c1, axis=1) - np.sum(c0 * c0, axis=1)
+    g = diff * np.sum(c1 * v1, axis=1) * u
+    a = np.asarray(accept, np.float64)
+    return float(np.sum(a * g) / max(np.sum(a), 1e-300))
+
+
+class LengthAdaptation:
+    """Adam (beta1 = 0, beta2 = 0.95, as in the reference implementation the paper uses)
+    ascending the ChEES gradient in log T, with rate 0.025 and the gradient taken w.r.t.
+    log T (g T); the averaged length follows the dual-averaging weights m^-kappa."""
+
+    def __init__(self, T0, rate=0.025, beta2=0.95, eps=1e-8, kappa=0.75):
+        self.logT = math.log(T0)
+        self.rate, self.beta2, self.eps, self.kappa = rate, beta2, eps, kappa
+        self.v = 0.0
+        self.m = 0
+        self.log_bar = self.logT
+
+    def update(self, grad_T):
+        self.m += 1
+        g = grad_T * math.exp(self.logT)  # d / d log T
+        self.v = self.beta2 * self.v + (1.0 - self.beta2) * g * g
+        vhat = self.v / (1.0 - self.beta2 ** self.m)
+        self.logT += self.rate * g / (math.sqrt(vhat) + self.eps)
+        eta = self.m ** (-self.kappa)
+        self.log_bar = eta * self.logT + (1.0 - eta) * self.log_bar
+        return math.exp(self.logT)
+
+    def final(self):
+        return math.exp(self.log_bar)
+
+
+def chees_run(fg, z, inv_mass, eps, T0, n_iter, rng, target=None):
+    """A plain HMC run with ChEES length adaptation at a fixed step size (for pins): every
+    iteration draws momenta, integrates for ceil(u T / eps) leapfrog steps, accepts, and
+    updates T. Returns the adaptation state and the final positions."""
+    z = np.array(z, np.float64)
+    inv_mass = np.asarray(inv_mass, np.float64)
+    chol_m = np.linalg.cholesky(np.linalg.inv(inv_mass)) if inv_mass.ndim == 2 else None
+    ad = LengthAdaptation(T0)
+    T = T0
+    for k in range(1, n_iter + 1):
+        n = rng.standard_normal(z.shape)
+        p = n @ chol_m.T if chol_m is not None else n / np.sqrt(inv_mass)
+        u = halton(k)
+        L = max(1, int(math.ceil(u * T / eps)))
+        z1, p1, f0, f1 = leapfrog_fn(fg, z, p, eps, L, inv_mass)
+        acc = accept_probability(hamiltonian(f0, p, inv_mass), hamiltonian(f1, p1, inv_mass))
+        T = ad.update(chees_gradient(z, z1, p1, inv_mass, acc, u))
+        keep = rng.uniform(size=len(z)) < acc
+        z = np.where(keep[:, None], z1, z)
+    return ad, z

@@ -351,14 +351,16 @@ class HMC:
     def __init__(self, model: Model, chains: int, n_leapfrog: int, n_burn: int, n_samples: int,
                  priors, step_size: float = 1e-2, target_accept: float = 0.75,
                  adapt_frac: float = 0.8, seed: int = 0, z0: torch.Tensor | None = None,
-                 inv_mass=None, mass_chol=None, stream=None):
+                 inv_mass=None, mass_chol=None, adapt_length: bool = False,
+                 max_leapfrog: int = 1000, stream=None):
         assert len(priors) == model.d
         self.model, self.C = model, chains
         self.n_burn, self.n_samples = n_burn, n_samples
         self._pa = make_priors(priors)
         o = _lib.HmcOpts(chains=chains, n_leapfrog=n_leapfrog, n_burn=n_burn,
                          n_samples=n_samples, step_size=step_size, target_accept=target_accept,
-                         adapt_frac=adapt_frac, seed=seed, priors=self._pa)
+                         adapt_frac=adapt_frac, seed=seed, priors=self._pa,
+                         adapt_length=int(adapt_length), max_leapfrog=max_leapfrog)
         if inv_mass is not None or mass_chol is not None:
             assert inv_mass is None or mass_chol is None
             im = np.ascontiguousarray(np.asarray(inv_mass if mass_chol is None else mass_chol,
@@ -394,7 +396,8 @@ class HMC:
         r = _lib.HmcInfo()
         check(lib().gl_hmc_get_info(self._h, ctypes.byref(r), _stream_ptr(stream)))
         return {"step_size": r.step_size, "accept_mean": r.accept_mean,
-                "trajectories": r.trajectories}
+                "trajectories": r.trajectories, "trajectory_length": r.trajectory_length,
+                "mean_leapfrog": r.mean_leapfrog}
 
     def leapfrog(self, z: torch.Tensor, p: torch.Tensor, L: int, eps: float, stream=None):
         """L leapfrog steps from (z, p) (no accept): returns z_L (FP64), p_L (FP32) and

@@ -58,12 +58,14 @@ class HmcOpts(ctypes.Structure):
                 ("n_samples", ctypes.c_int), ("step_size", ctypes.c_float),
                 ("target_accept", ctypes.c_float), ("adapt_frac", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("inv_mass", ctypes.POINTER(ctypes.c_float)),
+                ("adapt_length", ctypes.c_int), ("max_leapfrog", ctypes.c_int),
                 ("inv_mass_form", ctypes.c_int), ("priors", ctypes.POINTER(Prior))]
 
 
 class HmcInfo(ctypes.Structure):
     _fields_ = [("step_size", ctypes.c_float), ("accept_mean", ctypes.c_double),
-                ("trajectories", ctypes.c_int)]
+                ("trajectories", ctypes.c_int), ("trajectory_length", ctypes.c_float),
+                ("mean_leapfrog", ctypes.c_double)]
 
 
 class ViOpts(ctypes.Structure):

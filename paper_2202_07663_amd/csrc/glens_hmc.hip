@@ -60,6 +60,13 @@ struct HmcArgs {
   double* stats;       // sum of the chain-mean acceptance over sampled trajectories, count
   float* samples;      // [n_samples][C][d] physical parameters
   uint32_t seed_lo, seed_hi;
+  // trajectory-length adaptation (ChEES)
+  int adapt_len;       // 1: adapt T during the first n_adapt trajectories
+  float u;             // jitter of the current trajectory (t = u T)
+  float* T;            // trajectory length (device scalar)
+  double* la;          // log T, Adam second moment, update count, averaged log T
+  double* zbar;        // [2][d] chain means of the starts and of the proposals
+  float* cg;           // [C] ChEES gradient term of each chain
 };
 
 __device__ __forceinline__ float step_size(const HmcArgs& a) {
@@ -170,8 +177,23 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_begin_kernel(HmcArgs a) {
 }
 
 // Metropolis accept / reject and the sample record.
+// Chain means of the trajectory starts and of the proposals (one lane per parameter, chains
+// in order), for the ChEES gradient.
+__global__ void __launch_bounds__(kHmcThreads) hmc_mean_kernel(HmcArgs a) {
+  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+    double m0 = 0.0, m1 = 0.0;
+    for (int c = 0; c < a.C; ++c) {
+      m0 += a.zs[size_t(c) * a.d + j];
+      m1 += a.z[size_t(c) * a.d + j];
+    }
+    a.zbar[j] = m0 / a.C;
+    a.zbar[a.d + j] = m1 / a.C;
+  }
+}
+
 __global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
   __shared__ float s_p[kMaxParams], s_v[kMaxParams];
+  __shared__ double s_w[kMaxParams];
   __shared__ int s_keep;
   const int c = blockIdx.x;
   const int traj = *a.traj;
@@ -180,9 +202,29 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
   __syncthreads();
   chol_t_times(a, s_p, s_v);
   __syncthreads();
+  const bool chees = a.adapt_len && traj < a.n_adapt;
+  if (chees) {  // per coordinate: (z' - zbar')_j (M^-1 p')_j, M^-1 p' = chol (chol^T p')
+    for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+      float v = 0.f;
+      for (int i = 0; i <= j; ++i) v += a.chol[j * a.d + i] * s_v[i];
+      s_w[j] = (a.z[row + j] - a.zbar[a.d + j]) * double(v);
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     double k1 = 0.0;
     for (int j = 0; j < a.d; ++j) k1 += 0.5 * double(s_v[j]) * s_v[j];
+    if (chees) {  // (|z' - zbar'|^2 - |z - zbar|^2) ((z' - zbar') . M^-1 p') u
+      double d1 = 0.0, d0 = 0.0, dot = 0.0;
+      for (int j = 0; j < a.d; ++j) {
+        const double e1 = a.z[row + j] - a.zbar[a.d + j], e0 = a.zs[row + j] - a.zbar[j];
+        d1 += e1 * e1;
+        d0 += e0 * e0;
+        dot += s_w[j];
+      }
+      const double gc = (d1 - d0) * dot * a.u;
+      a.cg[c] = isfinite(gc) ? float(gc) : 0.f;
+    }
     const double h0 = -a.lps[c] + a.k0[c], h1 = -a.lp[c] + k1;
     double acc = exp(fmin(0.0, h0 - h1));
     if (a.bad[c] || !isfinite(h1) || !isfinite(acc)) acc = 0.0;
@@ -229,6 +271,28 @@ __global__ void hmc_adapt_kernel(HmcArgs a) {
     a.da[3] = m;
     *a.eps = float(traj + 1 == a.n_adapt ? exp(a.da[2]) : exp(log_eps));
   }
+  if (a.adapt_len && traj < a.n_adapt) {
+    // ChEES: acceptance-weighted mean gradient w.r.t. T, then Adam (beta1 = 0, beta2 =
+    // 0.95, rate 0.025) ascending in log T; the averaged log T uses the weights m^-kappa
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < a.C; ++c) {
+      num += double(a.accept[c]) * a.cg[c];
+      den += a.accept[c];
+    }
+    if (den > 0.0) {
+      const double m = a.la[2] + 1.0;
+      const double g = num / den * exp(a.la[0]);
+      const double v = 0.95 * a.la[1] + 0.05 * g * g;
+      const double vhat = v / (1.0 - pow(0.95, m));
+      const double logT = a.la[0] + 0.025 * g / (sqrt(vhat) + 1e-8);
+      const double eta = pow(m, -0.75);
+      a.la[0] = logT;
+      a.la[1] = v;
+      a.la[2] = m;
+      a.la[3] = eta * logT + (1.0 - eta) * a.la[3];
+    }
+    *a.T = float(traj + 1 == a.n_adapt ? exp(a.la[3]) : exp(a.la[0]));
+  }
   if (traj >= a.n_burn) {
     a.stats[0] += mean;
     a.stats[1] += 1.0;
@@ -267,6 +331,9 @@ using namespace glens;
 struct gl_hmc {
   gl_model* model = nullptr;
   int C = 0, d = 0, L = 1, n_burn = 0, n_samples = 0, n_adapt = 0, done = 0;
+  int max_leapfrog = 1000;
+  long long leapfrogs = 0;  // leapfrog steps run by gl_hmc_run
+  float T_fixed = 0.f, eps_fixed = 0.f;  // cached once adaptation has ended
   float target = 0.75f;
   uint64_t seed = 0;
   char* base = nullptr;
@@ -349,11 +416,44 @@ static int hmc_gradient(gl_hmc* h, float scale, int drift, hipStream_t st) {
   return hmc_chain_launch(hmc_grad_move_kernel, h->a, scale, drift, st);
 }
 
+// van der Corput sequence in base 2: the jitter of trajectory k (k >= 1).
+static double halton2(long long k) {
+  double f = 1.0, r = 0.0;
+  while (k > 0) {
+    f *= 0.5;
+    r += f * double(k & 1);
+    k >>= 1;
+  }
+  return r;
+}
+
 static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
   HmcArgs& a = h->a;
+  int L = h->L;
+  if (a.adapt_len) {
+    // L = ceil(u T / eps) with the jitter u shared by all chains; T and eps live on the
+    // device and change while they adapt, so they are read back until adaptation ends
+    float T = h->T_fixed, eps = h->eps_fixed;
+    if (h->done < h->n_adapt + 1 || !(T > 0.f)) {
+      GL_HIP(hipMemcpyAsync(&T, a.T, sizeof(float), hipMemcpyDeviceToHost, st));
+      GL_HIP(hipMemcpyAsync(&eps, a.eps, sizeof(float), hipMemcpyDeviceToHost, st));
+      GL_HIP(hipStreamSynchronize(st));
+      if (h->done >= h->n_adapt) {
+        h->T_fixed = T;
+        h->eps_fixed = eps;
+      }
+    }
+    const double u = halton2(h->done + 1);
+    a.u = float(u);
+    const double steps = std::ceil(u * double(T) / double(eps));
+    L = int(std::min(double(h->max_leapfrog), std::max(1.0, std::isfinite(steps) ? steps : 1.0)));
+  }
+  h->leapfrogs += L;
   int rc = hmc_launch1(hmc_begin_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
-  for (int l = 0; !rc && l < h->L; ++l)
-    rc = hmc_gradient(h, l + 1 < h->L ? 1.0f : 0.5f, l + 1 < h->L, st);
+  for (int l = 0; !rc && l < L; ++l)
+    rc = hmc_gradient(h, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);
+  if (!rc && a.adapt_len && h->done < h->n_adapt)
+    rc = hmc_launch1(hmc_mean_kernel, a, kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_finish_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_adapt_kernel, a, 1, 64, st);
   if (!rc) h->done++;
@@ -433,8 +533,8 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true);
   if (!rc) rc = fit_buffers_alloc(h->fb, C, d, pri.data());
   const size_t cd = size_t(C) * d;
-  const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 2 * C + 8) +
-                       sizeof(double) * (2 * cd + 3 * C + 8) +
+  const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 3 * C + 12) +
+                       sizeof(double) * (2 * cd + 3 * C + 12 + 2 * d) +
                        sizeof(float) * size_t(o->n_samples) * cd + 256 * 24;
   if (!rc && hipMalloc(&h->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
   if (rc) {
@@ -476,6 +576,12 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   a.stats = reinterpret_cast<double*>(take(sizeof(double) * 4));
   a.samples = o->n_samples ? reinterpret_cast<float*>(take(sizeof(float) * size_t(o->n_samples) * cd))
                            : nullptr;
+  a.T = reinterpret_cast<float*>(take(sizeof(float) * 4));
+  a.la = reinterpret_cast<double*>(take(sizeof(double) * 4));
+  a.zbar = reinterpret_cast<double*>(take(sizeof(double) * 2 * d));
+  a.cg = reinterpret_cast<float*>(take(sizeof(float) * C));
+  a.adapt_len = o->adapt_length ? 1 : 0;
+  h->max_leapfrog = o->max_leapfrog > 0 ? o->max_leapfrog : 1000;
   a.logl = m->ws.logl;
   a.grad = m->ws.grad;
   a.theta = m->ws.theta;
@@ -491,6 +597,10 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
             hipMemcpy(a.da, da0, sizeof(da0), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(a.stats, st0, sizeof(st0), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(a.eps, &eps0, sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  const float T0 = float(o->n_leapfrog) * o->step_size;
+  const double la0[4] = {std::log(double(T0)), 0.0, 0.0, std::log(double(T0))};
+  ok = ok && hipMemcpy(a.T, &T0, sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(a.la, la0, sizeof(la0), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && z0) ok = hipMemcpyAsync(a.z, z0, sizeof(double) * cd, hipMemcpyDeviceToDevice, st) == hipSuccess;
   if (!ok) rc = set_error(GL_E_DEVICE, "upload failed");
   if (!rc) rc = hmc_launch1(z0 ? hmc_round_kernel : hmc_start_kernel, a, int(cd), 256, st);
@@ -545,14 +655,17 @@ int gl_hmc_get_info(gl_hmc* h, gl_hmc_info* out, void* stream) {
   clear_error();
   if (!h || !out) return set_error(GL_E_INVALID, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  float eps = 0.f;
+  float eps = 0.f, T = 0.f;
   double stats[2] = {0.0, 0.0};
   GL_HIP(hipMemcpyAsync(&eps, h->a.eps, sizeof(float), hipMemcpyDeviceToHost, st));
+  GL_HIP(hipMemcpyAsync(&T, h->a.T, sizeof(float), hipMemcpyDeviceToHost, st));
   GL_HIP(hipMemcpyAsync(stats, h->a.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
   GL_HIP(hipStreamSynchronize(st));
   out->step_size = eps;
   out->accept_mean = stats[1] > 0 ? stats[0] / stats[1] : 0.0;
   out->trajectories = h->done;
+  out->trajectory_length = h->a.adapt_len ? T : float(h->L) * eps;
+  out->mean_leapfrog = h->done ? double(h->leapfrogs) / h->done : 0.0;
   return GL_OK;
 }
 

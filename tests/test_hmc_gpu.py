@@ -191,3 +191,38 @@ def test_sampler_from_prior_starts_and_bad_options(G, sie40):
         G.HMC(model, 4, 3, 1, 1, priors, inv_mass=bad)
     with pytest.raises(G.GlError):
         G.HMC(model, 4, 3, 1, 1, priors, target_accept=1.5)
+
+
+def test_trajectory_length_adaptation(G, sie40):
+    """With M^-1 = the posterior covariance the target is close to a standard normal in
+    whitened units, where the jittered ChEES criterion peaks at T* = 2.247 (tan 2T = 2T;
+    pinned on the oracle). Adapting eps and T over 80% of 300 burn-in trajectories lands near
+    T*, the jittered lengths average about T / (2 eps) steps, and the samples still match the
+    Laplace posterior."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    C, nb, ns = 64, 300, 200  # 500 trajectories, run 50 at a time
+    rng = np.random.default_rng(12)
+    z0 = z_c + rng.normal(size=(C, z_c.size)) @ np.linalg.cholesky(cov).T
+    model = G.Model.from_spec(spec, obs)
+    # a high acceptance target keeps eps small enough that L = ceil(u T / eps) resolves T
+    h = G.HMC(model, C, 5, nb, ns, priors, step_size=0.3, seed=13, inv_mass=cov,
+              z0=torch.from_numpy(z0).cuda(), adapt_length=True, target_accept=0.95)
+    Ts = []
+    for _ in range(10):
+        h.run(50)
+        Ts.append(round(h.info()["trajectory_length"], 3))
+    _say("T along the run", Ts)
+    info = h.info()
+    th = h.samples().cpu().numpy().astype(np.float64)
+    z = ofit.bijector_inverse(th.reshape(-1, th.shape[-1]), priors).reshape(th.shape)
+    sd = np.sqrt(np.diag(cov))
+    mean_err = np.abs(z.mean(axis=(0, 1)) - z_c) / sd
+    sd_ratio = z.std(axis=(0, 1)) / sd
+    _say("T", info["trajectory_length"], "eps", info["step_size"], "mean L",
+         info["mean_leapfrog"], "accept", info["accept_mean"], "mean err", mean_err.max(),
+         "sd ratio", sd_ratio.min(), sd_ratio.max(), "rhat", dg.split_rhat(z).max())
+    assert 1.6 < info["trajectory_length"] < 3.0
+    assert info["mean_leapfrog"] > 1.0
+    assert abs(info["accept_mean"] - 0.95) < 0.05
+    assert mean_err.max() < 0.15 and np.all(np.abs(sd_ratio - 1) < 0.12)
+    assert dg.split_rhat(z).max() < 1.05

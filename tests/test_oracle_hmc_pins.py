@@ -189,3 +189,30 @@ def test_dual_averaging_first_steps():
     da = hmc.DualAveraging(0.1, target=0.75)
     e1 = da.update(0.0)  # too large a step: shrink
     assert math.isclose(math.log(e1), math.log(1.0) - 0.75 / 11 / 0.05, rel_tol=1e-12)
+
+
+def test_van_der_corput_sequence():
+    assert [hmc.halton(k) for k in range(1, 9)] == [0.5, 0.25, 0.75, 0.125, 0.625, 0.375,
+                                                     0.875, 0.0625]
+
+
+# On a standard normal target with identity mass the flow is a rotation: with t = u T,
+# |z'|^2 - |z|^2 = sin^2 t (|p|^2 - |z|^2) + sin 2t z.p, so ChEES(t) = d sin^2 t, and the
+# jittered criterion E_u[d sin^2(u T)] = d (1/2 - sin 2T / (4T)) peaks where tan 2T = 2T.
+T_STAR = 4.493409457909064 / 2.0  # first positive root of tan x = x, halved
+
+
+@pytest.mark.parametrize("scale,inv_mass,want", [
+    (1.0, 1.0, T_STAR),          # standard normal, identity mass
+    (3.0, 1.0, 3.0 * T_STAR),    # the optimum scales with the target's width
+    (3.0, 9.0, T_STAR),          # ... and is T* again once M^-1 whitens the target
+])
+def test_chees_adaptation_finds_the_optimal_length(scale, inv_mass, want):
+    d = 4
+    fg = lambda z: (0.5 * np.sum(z * z, axis=1) / scale ** 2, z / scale ** 2)
+    rng = np.random.default_rng(1)
+    eps = 0.05 * scale / math.sqrt(inv_mass)
+    ad, z = hmc.chees_run(fg, scale * rng.standard_normal((512, d)), np.full(d, inv_mass),
+                          eps, 0.5 * want, 600, rng)
+    assert abs(ad.final() / want - 1.0) < 0.08, (ad.final(), want)
+    assert abs(np.std(z) / scale - 1.0) < 0.05  # still samples the target
