@@ -118,11 +118,12 @@ def workload():
 #            signal-to-noise of about 100 the paper quotes) with Table 1's sizes (300 x 300,
 #            500 x 1000, 50 chains x L = 5);
 #   epl60:   the 60x60 EPL + shapelet benchmark system with larger sizes (4096 x 300,
-#            1000 x 1000, 64 chains x L = 10).
+#            1000 x 1000, 64 chains x 1000 trajectories of L = 10, length not adapted).
 # ------------------------------------------------------------------------------------------
 
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
-                   chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100):
+                   chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100,
+                   adapt_length=True):
     import torch
     import synth
     import paper_2202_07663_amd as G
@@ -141,7 +142,7 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     chol = got["chol"].cpu().numpy()
     t2 = time.perf_counter()
     h = G.HMC(model, chains, L, n_burn, n_samples, priors, step_size=0.3, seed=seed + 3,
-              z0=z0, mass_chol=chol, adapt_length=True, max_leapfrog=max_leapfrog)
+              z0=z0, mass_chol=chol, adapt_length=adapt_length, max_leapfrog=max_leapfrog)
     h.run()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -405,7 +406,8 @@ def main():
         sp = synth.spec_paper80()
         out["pipeline"] = dict(workload="paper80_s6", **pipeline_bench(
             sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=1000, chains=50, L=5))
-        out["pipeline_epl60"] = dict(workload="epl60", **pipeline_bench(spec, *stored(spec)))
+        out["pipeline_epl60"] = dict(workload="epl60", **pipeline_bench(
+            spec, *stored(spec), adapt_length=False))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
     print(json.dumps(_finite(out), allow_nan=False), flush=True)
