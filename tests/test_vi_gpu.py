@@ -199,3 +199,27 @@ def test_map_vi_hmc_pipeline(G, systems):
     assert mean_err.max() < 0.3 and np.all(np.abs(sd_ratio - 1) < 0.1)
     assert np.all((vi_ratio > 0.5) & (vi_ratio < 2.0))
     assert pull.max() < 4.5
+
+
+def test_vi_options_and_non_finite_iterations(G, systems):
+    """Bad options are refused; running past K is refused; an iteration in which no sample
+    has a finite objective (an observed image of 1e30 counts/s) leaves the state as it was
+    and records a NaN loss."""
+    spec, obs, priors, fg, z_c, cov = systems["vi40"]
+    model = G.Model.from_spec(spec, obs)
+    for kw in ({"init_sd": 0.0}, {"lr_max": -1.0}, {"lr_warmup": -1}):
+        with pytest.raises(G.GlError):
+            G.VI(model, 8, 10, priors, z_c, **kw)
+    with pytest.raises(G.GlError):
+        G.VI(model, 0, 10, priors, z_c)
+    vi = G.VI(model, 8, 3, priors, z_c)
+    vi.step(3)
+    with pytest.raises(G.GlError):
+        vi.step(1)
+    bad = G.Model.from_spec(spec, np.full_like(obs, 1e30))
+    vi = G.VI(bad, 8, 2, priors, z_c, lr_warmup=0)
+    x0 = vi.get_state()["x"].cpu().numpy()
+    vi.step(2)
+    st = vi.get_state()
+    np.testing.assert_array_equal(st["x"].cpu().numpy(), x0)
+    assert np.all(np.isnan(st["loss"].cpu().numpy()))
