@@ -123,7 +123,7 @@ def workload():
 
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
                    chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100,
-                   adapt_length=True):
+                   adapt_length=True, vi_lr=1e-3, vi_warmup=500, vi_init_sd=1e-3):
     import torch
     import synth
     import paper_2202_07663_amd as G
@@ -134,8 +134,8 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     t0 = time.perf_counter()
     r = G.fit(model, n_map, k_map, priors, seed=seed)
     t1 = time.perf_counter()
-    vi = G.VI(model, n_vi, k_vi, priors, r["z_best"].astype(np.float64), lr_max=1e-3,
-              lr_warmup=500, init_sd=1e-3, seed=seed + 1)
+    vi = G.VI(model, n_vi, k_vi, priors, r["z_best"].astype(np.float64), lr_max=vi_lr,
+              lr_warmup=vi_warmup, init_sd=vi_init_sd, seed=seed + 1)
     vi.step()
     got = vi.get()
     z0 = vi.sample(chains, seed=seed + 2)
@@ -155,7 +155,7 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     grad_evals = n_map * k_map + n_vi * k_vi + round(chains * (n_burn + n_samples) *
                                                      info["mean_leapfrog"])
     return {
-        "config": {"map": [n_map, k_map], "vi": [n_vi, k_vi],
+        "config": {"map": [n_map, k_map], "vi": [n_vi, k_vi, vi_lr, vi_init_sd],
                    "hmc": {"chains": chains, "L": L, "burn": n_burn, "samples": n_samples}},
         "seconds": {"map": round(t1 - t0, 3), "vi": round(t2 - t1, 3), "hmc": round(t3 - t2, 3),
                     "total": round(t3 - t0, 3)},
