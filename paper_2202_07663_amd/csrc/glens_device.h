@@ -229,6 +229,19 @@ __host__ inline float rcp_f32(float x) { return 1.0f / x; }
 constexpr float kLn2f = 0.69314718055994531f;
 constexpr float kLog2e = 1.44269504088896341f;
 
+// A compile-time constant placed in scalar registers. In the polynomial loops below the
+// compiler would otherwise keep the FP64 coefficients in vector registers across the
+// sub-pixel loop and copy each into the accumulator of a two-operand FMA (an extra vector
+// move per term, and ~30 vector registers held). An empty asm statement that takes the
+// value in scalar registers makes it a scalar operand. Not volatile: the statement may be
+// moved and merged like any computation (a volatile one pins the schedule and costs more
+// than it saves).
+__device__ __forceinline__ double sconst(double c) {
+  asm("" : "+s"(c));
+  return c;
+}
+__host__ inline double sconst(double c) { return c; }
+
 GL_HD double log_f64(double x) {
   int e;
   double m = frexp(x, &e);  // [0.5, 1)
@@ -239,10 +252,10 @@ GL_HD double log_f64(double x) {
   const double s = (m - 1.0) * rcp_f64(m + 1.0);
   const double s2 = s * s;
   double p = 1.0 / 11.0;
-  p = fma(p, s2, 1.0 / 9.0);
-  p = fma(p, s2, 1.0 / 7.0);
-  p = fma(p, s2, 1.0 / 5.0);
-  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, sconst(1.0 / 9.0));
+  p = fma(p, s2, sconst(1.0 / 7.0));
+  p = fma(p, s2, sconst(1.0 / 5.0));
+  p = fma(p, s2, sconst(1.0 / 3.0));
   p = fma(p, s2, 1.0);
   const double de = double(e);
   return fma(de, kLn2, fma(de, kLn2Tail, 2.0 * s * p));
@@ -252,13 +265,13 @@ GL_HD double exp_f64(double x) {
   const double k = rint(x * kInvLn2);
   const double r = fma(-k, kLn2Tail, fma(-k, kLn2, x));
   double p = 1.0 / 3628800.0;  // 1/10!
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, sconst(1.0 / 362880.0));
+  p = fma(p, r, sconst(1.0 / 40320.0));
+  p = fma(p, r, sconst(1.0 / 5040.0));
+  p = fma(p, r, sconst(1.0 / 720.0));
+  p = fma(p, r, sconst(1.0 / 120.0));
+  p = fma(p, r, sconst(1.0 / 24.0));
+  p = fma(p, r, sconst(1.0 / 6.0));
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
