@@ -344,12 +344,19 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     }
   } else {
     const double yr = -Xr, yi = -Xi;
-    // Horner from the top, four terms per trip; coefficients past the series lengths are
-    // zero, so rounding the lengths up to a multiple of four is exact. The value series
+    // The coefficients are real, so each series is evaluated at the complex point y by
+    // synthetic division by the real quadratic (v - y)(v - conj y) = v^2 - 2 Re(y) v + |y|^2
+    // (Knuth, TAOCP vol. 2, sec. 4.6.4): b_n = c_n + 2 Re(y) b_(n+1) - |y|^2 b_(n+2) from the
+    // top down to n = 0, and the sum is b_0 - Re(y) b_1 + i Im(y) b_1. That is two real FMAs
+    // per term where complex Horner takes four. |y| = |eps| < 1, so rounding errors made
+    // early are damped as the recurrence runs down.
+    // Terms are taken four per trip; coefficients past the series lengths are zero, so
+    // rounding the lengths up to a multiple of four is exact. The value series
     // S(y) = sum c_n y^n runs in FP64 over all terms; the adjoint's derivative series
-    // S'(y) = sum (n+1) c_{n+1} y^n and dS/dt = sum dc_n y^n run in FP32 over the first
+    // S'(y) = sum (n+1) c_(n+1) y^n and dS/dt = sum dc_n y^n run in FP32 over the first
     // nterms_d terms only.
-    double sr = 0.0, si = 0.0;
+    const double r2 = 2.0 * yr, yy = fma(yr, yr, yi * yi);
+    double b1 = 0.0, b2 = 0.0;  // b_(n+1), b_(n+2)
     const int nt4 = (c.nterms + 3) & ~3;
     // dS/dX: by its series only for small |eps|; otherwise from S below. dS/dt (EPL): always
     // by its series.
@@ -358,29 +365,29 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     for (int n0 = nt4 - 4; n0 >= nd4; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
-        const double nsr = fma(sr, yr, fma(-si, yi, cs[n0 + q]));
-        si = fma(sr, yi, si * yr);
-        sr = nsr;
+        const double b0 = fma(r2, b1, fma(-yy, b2, cs[n0 + q]));
+        b2 = b1;
+        b1 = b0;
       }
     }
     if (ADJ) {
-      const float yrf = float(yr), yif = float(yi);
-      float dr = 0.f, di = 0.f, tr = 0.f, ti = 0.f;
+      const float r2f = float(r2), yyf = float(yy);
+      float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
       if (sx_series) {
         for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
           for (int q = 3; q >= 0; --q) {
             const int n = n0 + q;
-            const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
-            si = fma(sr, yi, si * yr);
-            sr = nsr;
-            const float ndr = fmaf(dr, yrf, fmaf(-di, yif, ncs[n]));
-            di = fmaf(dr, yif, di * yrf);
-            dr = ndr;
+            const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
+            b2 = b1;
+            b1 = b0;
+            const float d0 = fmaf(r2f, d1, fmaf(-yyf, d2, ncs[n]));
+            d2 = d1;
+            d1 = d0;
             if (MASS == 1) {
-              const float ntr = fmaf(tr, yrf, fmaf(-ti, yif, dcs[n]));
-              ti = fmaf(tr, yif, ti * yrf);
-              tr = ntr;
+              const float t0 = fmaf(r2f, t1, fmaf(-yyf, t2, dcs[n]));
+              t2 = t1;
+              t1 = t0;
             }
           }
         }
@@ -389,18 +396,27 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
 #pragma unroll
           for (int q = 3; q >= 0; --q) {
             const int n = n0 + q;
-            const double nsr = fma(sr, yr, fma(-si, yi, cs[n]));
-            si = fma(sr, yi, si * yr);
-            sr = nsr;
-            const float ntr = fmaf(tr, yrf, fmaf(-ti, yif, dcs[n]));
-            ti = fmaf(tr, yif, ti * yrf);
-            tr = ntr;
+            const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
+            b2 = b1;
+            b1 = b0;
+            const float t0 = fmaf(r2f, t1, fmaf(-yyf, t2, dcs[n]));
+            t2 = t1;
+            t1 = t0;
           }
         }
+      }
+      const float yrf = float(yr), yif = float(yi);
+      const float tr = fmaf(-yrf, t2, t1), ti = yif * t2;
+      float dr, di;
+      if (sx_series) {
+        dr = fmaf(-yrf, d2, d1);
+        di = yif * d2;
+      } else {
         // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
         //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S,
         // (as series: the coefficient of (-X)^n on both sides agrees for every n). The
         // numerator cancels like |X| = |eps|, so it is formed in FP64 from the FP64 S.
+        const double sr = fma(-yr, b2, b1), si = yi * b2;
         const double h = 0.5 * c.t;
         const double xsr = Xr * sr - Xi * si, xsi = Xr * si + Xi * sr;
         const float numr = float((1.0 - h) * (1.0 - sr) - h * xsr);
@@ -413,8 +429,8 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
       m.SX = {-dr, -di};  // d/dX = -d/dy
       m.St = {tr, ti};
     }
-    Sr = sr;
-    Si = si;
+    Sr = fma(-yr, b2, b1);
+    Si = yi * b2;
     A = exp_f64(c.tlnb - 0.5 * c.t * lnw2);
   }
   const double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
