@@ -70,6 +70,12 @@ GL_HD void clamp_eps(double e1, double e2, double emax, double& c1, double& c2, 
   }
 }
 
+// r_n = sqrt(2^n / n!) for n = 0 .. kMaxNmax; r_n1 r_n2 scales coefficient (n1, n2).
+constexpr double kHermR[kMaxNmax + 1] = {
+    1.0, 1.4142135623730951, 1.4142135623730951, 1.1547005383792515, 0.816496580927726,
+    0.5163977794943222, 0.29814239699997197, 0.15936381457791915, 0.07968190728895957};
+GL_HD inline double hermite_scale(int n1, int n2) { return kHermR[n1] * kHermR[n2]; }
+
 GL_HD void decode_light(const float* th, LightC& L) {
   const double re = th[0], n = th[1];
   double e1, e2, j11, j12, j22;
@@ -190,8 +196,10 @@ GL_HD void decode_lights(const float* th, int mass, int shear, int lens_light, i
     const double beta = th[p++];
     c.beta = float(beta);
     c.inv_beta = float(1.0 / beta);
-    const int M = (nmax + 1) * (nmax + 2) / 2;
-    for (int k = 0; k < M; ++k) c.shp[k] = float(double(th[p + k]) / beta * 0.56418958354775628);
+    const double f = 0.56418958354775628 / beta;  // 1 / (beta sqrt(pi))
+    for (int n = 0, k = 0; n <= nmax; ++n)
+      for (int n2 = 0; n2 <= n; ++n2, ++k)
+        c.shp[k] = float(double(th[p + k]) * (f * hermite_scale(n - n2, n2)));
   }
 }
 
@@ -530,15 +538,17 @@ GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc
   return I;
 }
 
-// Normalised Hermite polynomials h_n = phi_n / phi_0 (phi_n the Hermite functions):
-// h_0 = 1, h_1 = sqrt(2) u, h_{n+1} = sqrt(2/(n+1)) u h_n - sqrt(n/(n+1)) h_{n-1}.
+// Scaled Hermite polynomials g_n(u) = H_n(u) / 2^n (H_n the physicists' polynomials):
+// g_0 = 1, g_1 = u, g_(n+1) = u g_n - (n/2) g_(n-1), two operations per step, and
+// g_n' = n g_(n-1). The Hermite functions are phi_n = (2^n n! sqrt(pi))^(-1/2) H_n e^(-u^2/2)
+// = pi^(-1/4) r_n g_n e^(-u^2/2) with r_n = sqrt(2^n / n!); the coefficients carry r_n1 r_n2
+// (hermite_scale) so that the sums run over the g_n directly.
 template <int NMAX>
 GL_HD void hermite(float u, float* h) {
   h[0] = 1.0f;
-  if (NMAX >= 1) h[1] = 1.41421356237f * u;
+  if (NMAX >= 1) h[1] = u;
 #pragma unroll
-  for (int n = 1; n < NMAX; ++n)
-    h[n + 1] = sqrtf(2.0f / (n + 1)) * u * h[n] - sqrtf(float(n) / (n + 1)) * h[n - 1];
+  for (int n = 1; n < NMAX; ++n) h[n + 1] = fmaf(u, h[n], -(0.5f * n) * h[n - 1]);
 }
 
 // Index of coefficient (n1, n2) in the order n = 0..NMAX, n1 = n..0, n2 = n - n1.
@@ -547,15 +557,16 @@ __host__ __device__ constexpr int shp_index(int n1, int n2) {
 }
 
 // Shapelet intensity at offset (sdx, sdy) from the source centre:
-// G(u, v) sum_k c'_k h_n1(u) h_n2(v), c'_k = c_k / (beta sqrt(pi)), G = exp(-(u^2+v^2)/2),
-// summed as U = sum_n1 h_n1(u) T_n1 with T_n1 = sum_n2 c'_(n1,n2) h_n2(v).
+// G(u, v) sum_k c'_k g_n1(u) g_n2(v), c'_k = c_k r_n1 r_n2 / (beta sqrt(pi)),
+// G = exp(-(u^2+v^2)/2), summed as U = sum_n1 g_n1(u) T_n1 with
+// T_n1 = sum_n2 c'_(n1,n2) g_n2(v).
 template <int NMAX>
 GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
   const float u = sdx * c.inv_beta, v = sdy * c.inv_beta;
   float hu[NMAX + 1], hv[NMAX + 1];
   hermite<NMAX>(u, hu);
   hermite<NMAX>(v, hv);
-  // h_0 = 1: every sum starts from its n = 0 term (no addition of a zero, which the
+  // g_0 = 1: every sum starts from its n = 0 term (no addition of a zero, which the
   // compiler must keep for signed zeros)
   float U = 0.f;
 #pragma unroll
@@ -569,11 +580,11 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
 }
 
 // Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y), using
-// h_n' = sqrt(2n) h_{n-1} for the normalised Hermite polynomials:
-//   dI/du = G (sum_n1 sqrt(2 n1) h_{n1-1}(u) T_n1 - u U),
-//   dI/dv = G (sum_n1 h_n1(u) Tv_n1 - v U),  Tv_n1 = sum_n2 c' sqrt(2 n2) h_{n2-1}(v),
-//   dI/dc_k = G h_n1(u) h_n2(v) / (beta sqrt(pi)) (the 1/(beta sqrt(pi)) is applied when
-//   the accumulators are mapped onto the gradient).
+// g_n' = n g_(n-1) for the scaled Hermite polynomials:
+//   dI/du = G (sum_n1 n1 g_(n1-1)(u) T_n1 - u U),
+//   dI/dv = G (sum_n1 g_n1(u) Tv_n1 - v U),  Tv_n1 = sum_n2 c'_(n1,n2) n2 g_(n2-1)(v),
+//   dI/dc_k = G g_n1(u) g_n2(v) r_n1 r_n2 / (beta sqrt(pi)) (the factor r_n1 r_n2 /
+//   (beta sqrt(pi)) is applied when the accumulators are mapped onto the gradient).
 template <int NMAX>
 GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float* acc, float& gbx,
                          float& gby) {
@@ -584,7 +595,7 @@ GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float*
   hermite<NMAX>(v, hv);
   const float G = exp2_f32(-0.5f * kLog2e * (u * u + v * v));
   const float sg = sb * G;
-  // h_0 = 1: sums start from their first term (see shapelet_fwd)
+  // g_0 = 1: sums start from their first term (see shapelet_fwd)
   float U = 0.f, Uu = 0.f, Uv = 0.f;
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1) {
@@ -593,11 +604,11 @@ GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float*
     for (int n2 = 1; n2 <= NMAX - n1; ++n2) {
       const float ck = c.shp[shp_index(n1, n2)];
       T = fmaf(ck, hv[n2], T);
-      Tv = n2 == 1 ? ck * 1.41421356237f : fmaf(ck, sqrtf(2.0f * n2) * hv[n2 - 1], Tv);
+      Tv = n2 == 1 ? ck : fmaf(ck, float(n2) * hv[n2 - 1], Tv);
     }
     U = n1 == 0 ? T : fmaf(hu[n1], T, U);
     if (n1 < NMAX) Uv = n1 == 0 ? Tv : fmaf(hu[n1], Tv, Uv);
-    if (n1 > 0) Uu = n1 == 1 ? 1.41421356237f * T : fmaf(sqrtf(2.0f * n1) * hu[n1 - 1], T, Uu);
+    if (n1 > 0) Uu = n1 == 1 ? T : fmaf(float(n1) * hu[n1 - 1], T, Uu);
   }
   float hvs[NMAX + 1];
 #pragma unroll
@@ -650,9 +661,10 @@ GL_HD int map_gradient(const PConst& c, const double* a, int mass, int shear, in
   j += 7;
   if (nmax >= 0) {
     gr[j++] = float(a[A_SHP_BETA]);
-    const int M = (nmax + 1) * (nmax + 2) / 2;
     const double f = double(c.inv_beta) * kInvSqrtPi;
-    for (int q = 0; q < M; ++q) gr[j++] = float(a[A_SHP_C + q] * f);
+    for (int n = 0, q = 0; n <= nmax; ++n)
+      for (int n2 = 0; n2 <= n; ++n2, ++q)
+        gr[j++] = float(a[A_SHP_C + q] * f * hermite_scale(n - n2, n2));
   }
   return j;
 }

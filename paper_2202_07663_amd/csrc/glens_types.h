@@ -76,7 +76,7 @@ struct PConst {
   float mj11, mj12, mj22;
   LightC lens, src;
   float beta, inv_beta;
-  float shp[kMaxShp];  // c_k / (beta sqrt(pi))
+  float shp[kMaxShp];  // c_k r_n1 r_n2 / (beta sqrt(pi)), r_n = sqrt(2^n / n!)
   float dc[kMaxTerms]; // d c_n / dt (zero from nterms_d on)
   float nc[kMaxTerms]; // (n + 1) c_{n+1}: coefficients of dS/dy (zero from nterms_d - 1 on)
 };
