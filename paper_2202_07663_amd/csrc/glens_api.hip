@@ -237,31 +237,34 @@ void conv_bands(int P, int H, int* bands, int* band_rows) {
   *bands = (H + *band_rows - 1) / *band_rows;
 }
 
-int subpix_key(const ModelCfg& c) { return c.mass * 16 + (c.nmax + 1); }
+int subpix_key(const ModelCfg& c) { return (c.mass * 2 + c.lens_light) * 16 + (c.nmax + 1); }
 
 // ------------------------------------------------------------------------------------------
 // kernel dispatch
 // ------------------------------------------------------------------------------------------
 using GroupKernel = void (*)(Group);
 
-template <int MASS, int NMAX>
+template <int MASS, int LL, int NMAX>
 struct SubKernels {
-  static constexpr GroupKernel fwd = subpix_fwd_kernel<MASS, NMAX>;
-  static constexpr GroupKernel adj = subpix_adj_kernel<MASS, NMAX>;
+  static constexpr GroupKernel fwd = subpix_fwd_kernel<MASS, LL, NMAX>;
+  static constexpr GroupKernel adj = subpix_adj_kernel<MASS, LL, NMAX>;
 };
 
-template <int MASS, int... N>
+template <int MASS, int LL, int... N>
 static void fill_sub(GroupKernel* f, GroupKernel* a, std::integer_sequence<int, N...>) {
-  ((f[MASS * 16 + N] = SubKernels<MASS, N - 1>::fwd), ...);
-  ((a[MASS * 16 + N] = SubKernels<MASS, N - 1>::adj), ...);
+  ((f[(MASS * 2 + LL) * 16 + N] = SubKernels<MASS, LL, N - 1>::fwd), ...);
+  ((a[(MASS * 2 + LL) * 16 + N] = SubKernels<MASS, LL, N - 1>::adj), ...);
 }
 
+// indexed by subpix_key
 struct SubTable {
-  GroupKernel fwd[32] = {};
-  GroupKernel adj[32] = {};
+  GroupKernel fwd[64] = {};
+  GroupKernel adj[64] = {};
   SubTable() {
-    fill_sub<0>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
-    fill_sub<1>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+    fill_sub<0, 0>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+    fill_sub<0, 1>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+    fill_sub<1, 0>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
+    fill_sub<1, 1>(fwd, adj, std::make_integer_sequence<int, kMaxNmax + 2>{});
   }
 };
 static const SubTable& sub_table() {

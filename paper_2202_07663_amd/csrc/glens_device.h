@@ -131,6 +131,8 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   c.epsabs = eabs;
   c.theta_e = float(theta_e);
   c.tf = float(t);
+  c.hp = float(1.0 - 0.5 * t);
+  c.hm = float(-0.5 * t);
   c.e1f = float(e1);
   c.e2f = float(e2);
   c.lnb = float(log(B));
@@ -461,11 +463,10 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
 // (already weighted by the pixel adjoint). beta = x - alpha - alpha_ext.
 template <int MASS>
 GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, Cx g, float* acc) {
-  const float t = c.tf;
   // Wirtinger derivatives of alpha w.r.t. w and conj(w) (eps fixed)
   const Cx XSX = cmul(m.X, m.SX);
-  Cx P1 = cadd(cscale(m.S, 1.0f - 0.5f * t), XSX);
-  Cx P2 = csub(cscale(m.S, -0.5f * t), XSX);
+  Cx P1 = cadd(cscale(m.S, c.hp), XSX);  // (1 - t/2) S + X S_X
+  Cx P2 = csub(cscale(m.S, c.hm), XSX);  // -(t/2) S - X S_X
   if (m.floored) {  // |w|^2 frozen at the floor: X = conj(eps) w^2 / floor
     P1 = cadd(m.S, cscale(XSX, 2.0f));
     P2 = {0.f, 0.f};

@@ -63,7 +63,7 @@ void system_free(SystemData& sd);
 SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles);
 
 // Kernel configuration key of a system (systems with equal keys share launches).
-int subpix_key(const ModelCfg& c);  // mass * 16 + (nmax + 1)
+int subpix_key(const ModelCfg& c);  // (mass * 2 + lens_light) * 16 + (nmax + 1)
 
 // Launch stages over a group of systems (all with the same key / PSF size).
 int launch_prologue(const Group& g, hipStream_t st);

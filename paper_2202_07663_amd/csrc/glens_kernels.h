@@ -83,18 +83,20 @@ __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float
   __syncthreads();
 }
 
-template <int MASS, int NMAX>
-__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c,
-                                                    int lens_light, double x, double y) {
+template <int MASS, int LL, int NMAX>
+__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
+                                                    double y) {
   MassState m;
   mass_eval<MASS, false>(c, s_c, nullptr, nullptr, x, y, m);
   float v = sersic_fwd(c.src, m.sdx, m.sdy);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy);
-  if (lens_light) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
+  if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
   return v;
 }
 
-template <int MASS, int NMAX>
+// MASS: 0 SIE, 1 EPL; LL: lens light on (1) or off (0); NMAX: shapelet order (-1: none).
+// Every system of one launch has the same (MASS, LL, NMAX).
+template <int MASS, int LL, int NMAX>
 __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int si = find_sys(g, blockIdx.x);
   const SysDesc& s = g.sys[si];
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
       const double y = s.y0 + double(i * k + a) * s.dxs;
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
-        sum += surface_brightness<MASS, NMAX>(c, s_c, s.lens_light, x, y);
+        sum += surface_brightness<MASS, LL, NMAX>(c, s_c, x, y);
       }
     }
     out[pix] = sum * s.inv_k2;
@@ -460,7 +462,7 @@ __device__ __forceinline__ void wave_sums(const float* acc, double* out) {
   }
 }
 
-template <int MASS, int NMAX>
+template <int MASS, int LL, int NMAX>
 __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3)))
 subpix_adj_kernel(Group g) {
   constexpr int NS = n_slots<NMAX>();
@@ -499,7 +501,7 @@ subpix_adj_kernel(Group g) {
         }
         acc[A_SRC + L_DX] += sb * gx;
         acc[A_SRC + L_DY] += sb * gy;
-        if (s.lens_light) {
+        if (LL) {
           float lx, ly;
           sersic_adj(c.lens, float(x - c.lxs), float(y - c.lys), sb, acc + A_LENS, lx, ly);
           acc[A_LENS + L_DX] += sb * lx;

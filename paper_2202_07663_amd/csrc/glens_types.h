@@ -70,6 +70,7 @@ struct PConst {
   double lxs, lys;     // lens-light centre
   // FP32 part
   float theta_e, tf;   // Einstein radius, t
+  float hp, hm;        // 1 - t/2, -t/2
   float e1f, e2f;
   float lnb;
   float tfac;          // t / (2 (1 - |eps|^2))
