@@ -508,7 +508,8 @@ struct LightEval {
 };
 
 GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
-  float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
+  // R^2 = dx (qa dx + qb dy) + qc dy^2
+  float q = fmaf(dx, fmaf(L.qb, dy, L.qa * dx), L.qc * dy * dy);
   q = q < kR2Floor ? kR2Floor : q;
   // rho = (R / R_eff)^(1/n) = 2^(log2(R^2) / (2n) - log2(R_eff) / n);  I = I0 e^(b_n (1 - rho))
   const float rho = exp2_f32(fmaf(log2_f32(q), L.inv2n, -L.l2re_n));

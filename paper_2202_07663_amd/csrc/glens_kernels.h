@@ -96,6 +96,27 @@ __device__ __forceinline__ float surface_brightness(const PConst& c, const doubl
 
 // MASS: 0 SIE, 1 EPL; LL: lens light on (1) or off (0); NMAX: shapelet order (-1: none).
 // Every system of one launch has the same (MASS, LL, NMAX).
+// The pixels [p0, p1) of one particle's model image. The restrict qualifiers tell the compiler
+// that the image stores do not write the particle's constants, which then stay scalar loads.
+template <int MASS, int LL, int NMAX>
+__device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* __restrict__ c,
+                                               const double* s_c, float* __restrict__ out,
+                                               int p0, int p1) {
+  const int W = s.W, k = s.k;
+  for (int pix = p0 + threadIdx.x; pix < p1; pix += blockDim.x) {
+    const int i = pix / W, j = pix - i * W;
+    float sum = 0.f;
+    for (int a = 0; a < k; ++a) {
+      const double y = s.y0 + double(i * k + a) * s.dxs;
+      for (int b = 0; b < k; ++b) {
+        const double x = s.x0 + double(j * k + b) * s.dxs;
+        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y);
+      }
+    }
+    out[pix] = sum * s.inv_k2;
+  }
+}
+
 template <int MASS, int LL, int NMAX>
 __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int si = find_sys(g, blockIdx.x);
@@ -106,22 +127,10 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   __shared__ double s_c[kMaxTerms];
   __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
   stage_series(c, s_c, s_nc, s_dc);
-  const int HW = s.H * s.W, W = s.W, k = s.k;
+  const int HW = s.H * s.W;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
-  float* out = s.m0 + (size_t)part * HW;
-  for (int pix = p0 + threadIdx.x; pix < p1; pix += blockDim.x) {
-    const int i = pix / W, j = pix - i * W;
-    float sum = 0.f;
-    for (int a = 0; a < k; ++a) {
-      const double y = s.y0 + double(i * k + a) * s.dxs;
-      for (int b = 0; b < k; ++b) {
-        const double x = s.x0 + double(j * k + b) * s.dxs;
-        sum += surface_brightness<MASS, LL, NMAX>(c, s_c, x, y);
-      }
-    }
-    out[pix] = sum * s.inv_k2;
-  }
+  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, p0, p1);
 }
 
 // ------------------------------------------------------------------------------------------
