@@ -108,6 +108,12 @@ int validate_desc(const gl_model_desc* d, ModelCfg* c) {
   return GL_OK;
 }
 
+static uint16_t f16_bits(_Float16 h) {
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
 int system_upload(const gl_model_desc* d, const ModelCfg& cfg, SystemData& sd) {
   sd.cfg = cfg;
   const int KK = cfg.K * cfg.K, HW = cfg.H * cfg.W;
@@ -118,19 +124,53 @@ int system_upload(const gl_model_desc* d, const ModelCfg& cfg, SystemData& sd) {
   GL_HIP(hipMalloc(&sd.psf_flip, sizeof(float) * KK));
   GL_HIP(hipMemcpy(sd.psf, d->psf, sizeof(float) * KK, hipMemcpyHostToDevice));
   GL_HIP(hipMemcpy(sd.psf_flip, flip.data(), sizeof(float) * KK, hipMemcpyHostToDevice));
+  size_t tab_bytes = 0;
+  if (cfg.K <= kMfmaMaxK) {
+    // Toeplitz operands of the matrix-core PSF pass, per direction (0: flipped PSF, forward;
+    // 1: PSF, adjoint), PSF row a and lane l = n + 16 g: elements e = 0..7 of column n,
+    // rows 8g + e, of T_a[kk][n] = psf[a][kk - n] 2^t (zero outside 0 <= kk - n < K, n < N),
+    // as two fp16 parts (v = h + l, l from the exact FP32 remainder); 2^t brings the largest
+    // tap into [2^14, 2^15).
+    const int K = cfg.K, N = mfma_geom(cfg.H, cfg.W, K).N;
+    float pmax = 0.f;
+    for (int i = 0; i < KK; ++i) pmax = std::max(pmax, std::fabs(d->psf[i]));
+    int e = 0;
+    if (pmax > 0.f) std::frexp(pmax, &e);
+    sd.psf_mfma_exp = pmax > 0.f ? 15 - e : 0;
+    std::vector<uint16_t> tab(size_t(2) * K * 64 * 16, 0);
+    for (int dir = 0; dir < 2; ++dir) {
+      const float* kf = dir == 0 ? flip.data() : d->psf;
+      for (int a = 0; a < K; ++a)
+        for (int l = 0; l < 64; ++l)
+          for (int e8 = 0; e8 < 8; ++e8) {
+            const int n = l % 16, b = 8 * (l / 16) + e8 - n;
+            const float v = (n < N && b >= 0 && b < K) ? std::ldexp(kf[a * K + b], sd.psf_mfma_exp)
+                                                       : 0.f;
+            const size_t o = ((size_t(dir) * K + a) * 64 + l) * 16;
+            const _Float16 h = static_cast<_Float16>(v);
+            tab[o + e8] = f16_bits(h);
+            tab[o + 8 + e8] = f16_bits(static_cast<_Float16>(v - static_cast<float>(h)));
+          }
+    }
+    tab_bytes = sizeof(uint16_t) * tab.size();
+    GL_HIP(hipMalloc(&sd.psf_mfma, tab_bytes));
+    GL_HIP(hipMemcpy(sd.psf_mfma, tab.data(), tab_bytes, hipMemcpyHostToDevice));
+  }
   sd.has_obs = d->obs != nullptr;
   GL_HIP(hipMalloc(&sd.obs, sizeof(float) * HW));
   if (d->obs) GL_HIP(hipMemcpy(sd.obs, d->obs, sizeof(float) * HW, hipMemcpyHostToDevice));
   else GL_HIP(hipMemset(sd.obs, 0, sizeof(float) * HW));
-  sd.bytes = sizeof(float) * (2 * KK + HW);
+  sd.bytes = sizeof(float) * (2 * KK + HW) + tab_bytes;
   return GL_OK;
 }
 
 void system_free(SystemData& sd) {
   if (sd.psf) (void)hipFree(sd.psf);
   if (sd.psf_flip) (void)hipFree(sd.psf_flip);
+  if (sd.psf_mfma) (void)hipFree(sd.psf_mfma);
   if (sd.obs) (void)hipFree(sd.obs);
   sd.psf = sd.psf_flip = sd.obs = nullptr;
+  sd.psf_mfma = nullptr;
 }
 
 int choose_tiles(int P, int HW) {
@@ -217,6 +257,8 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.obs = sd.obs;
   s.psf = sd.psf;
   s.psf_flip = sd.psf_flip;
+  s.psf_mfma = sd.psf_mfma;
+  s.psf_mfma_exp = sd.psf_mfma_exp;
   s.pc = ws.pc;
   s.m0 = ws.m0;
   s.sbar = ws.sbar;
@@ -224,6 +266,11 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.seed = ws.seed;
   s.lpart = ws.lpart;
   conv_bands(P, c.H, &s.bands, &s.band_rows);
+  // matrix-core PSF pass for whole-image launches when the image's tiles and LDS fit; the
+  // choice depends on this system alone, so its results do not depend on its launch partners
+  const MfmaGeom q = mfma_geom(c.H, c.W, c.K);
+  s.conv_mfma = sd.psf_mfma && s.bands == 1 && q.T <= 4 * kMfmaWaveTiles &&
+                size_t(mfma_lds_bytes(q, c.H, c.W)) <= kConvLdsMax;
   return s;
 }
 
@@ -333,17 +380,28 @@ static int conv_lds_limit(size_t lds) {
       for (int i = 0; i < (GL_MAX_PSF + 1) / 2; ++i) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tab[i]),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024 - 256);
+                                           int(kConvLdsMax));
         if (e != hipSuccess) attr_err = e;
       }
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(conv_mfma_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(kConvLdsMax));
+    if (e != hipSuccess) attr_err = e;
   });
   if (attr_err != hipSuccess && lds > 64 * 1024)
     return set_error(GL_E_DEVICE, "cannot raise the LDS limit: %s", hipGetErrorString(attr_err));
   return GL_OK;
 }
 
+static int launch_conv_mfma(const Group& g, size_t lds, hipStream_t st) {
+  int rc = conv_lds_limit(lds);
+  if (rc) return rc;
+  return launch(conv_mfma_kernel, g.block0[g.nsys], kConvThreads, lds, g, st);
+}
+
 int launch_conv(int K, const Group& g, size_t lds, hipStream_t st) {
   for (int i = 0; i < g.nsys; ++i) {
+    if (g.sys[i].conv_mfma) continue;
     const int nstrip = (g.sys[i].H + kConvRows - 1) / kConvRows;
     if (nstrip * g.sys[i].W > kConvMaxStrips * kConvThreads)
       return set_error(GL_E_UNIMPLEMENTED, "image too large for the PSF kernel");
@@ -371,18 +429,19 @@ static int launch_conv_band(int K, Group& g, int mode, hipStream_t st) {
   size_t lds = 0;
   for (int i = 0; i < g.nsys; ++i) {
     const SysDesc& s = g.sys[i];
+    if (s.conv_mfma) continue;
     const int nsr = s.band_rows / kConvRows;
     lds = std::max(lds, sizeof(float) * size_t((nsr * kConvRows + K - 1) | 1) * (s.W + K - 1));
   }
   int rc = conv_lds_limit(lds);
   if (rc) return rc;
-  set_blocks(g, blocks_conv_band);
+  set_blocks(g, [](const SysDesc& s) { return s.conv_mfma ? 0 : blocks_conv_band(s); });
   if ((rc = launch(conv_table().band[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st)))
     return rc;
   if (mode == 2)
     return launch(conv_table().band_adj[(K - 1) / 2], g.block0[g.nsys], kConvThreads, lds, g, st);
   if (mode == 1) {
-    set_blocks(g, [](const SysDesc& s) { return (s.P + 63) / 64; });
+    set_blocks(g, [](const SysDesc& s) { return s.conv_mfma ? 0 : (s.P + 63) / 64; });
     return launch(conv_band_sum_kernel, g.block0[g.nsys], 64, 0, g, st);
   }
   return GL_OK;
@@ -398,17 +457,30 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev
   set_blocks(g, blocks_subpix);
   if ((rc = launch_subpix_fwd(key, g, st))) return rc;
   GL_HIP(mark(2));
-  size_t lds = 0;
-  bool banded = false;
+  // PSF pass: systems flagged for matrix cores in one launch, the others in the banded or the
+  // whole-image VALU kernels (a system with one band gets the same bits from either)
+  size_t lds = 0, lds_mfma = 0;
+  bool banded = false, any_mfma = false, any_valu = false;
   for (int i = 0; i < g.nsys; ++i) {
-    g.sys[i].mode = mode;
-    lds = std::max(lds, conv_lds_bytes(g.sys[i].H, g.sys[i].W, K, mode));
-    banded = banded || g.sys[i].bands > 1;
+    SysDesc& s = g.sys[i];
+    s.mode = mode;
+    if (s.conv_mfma) {
+      any_mfma = true;
+      lds_mfma = std::max(lds_mfma, size_t(mfma_lds_bytes(mfma_geom(s.H, s.W, s.K), s.H, s.W)));
+    } else {
+      any_valu = true;
+      lds = std::max(lds, conv_lds_bytes(s.H, s.W, K, mode));
+      banded = banded || s.bands > 1;
+    }
   }
-  if (banded) {
+  if (any_mfma) {
+    set_blocks(g, [](const SysDesc& s) { return s.conv_mfma ? blocks_conv(s) : 0; });
+    if ((rc = launch_conv_mfma(g, lds_mfma, st))) return rc;
+  }
+  if (any_valu && banded) {
     if ((rc = launch_conv_band(K, g, mode, st))) return rc;
-  } else {
-    set_blocks(g, blocks_conv);
+  } else if (any_valu) {
+    set_blocks(g, [](const SysDesc& s) { return s.conv_mfma ? 0 : blocks_conv(s); });
     if ((rc = launch_conv(K, g, lds, st))) return rc;
   }
   GL_HIP(mark(3));

@@ -52,6 +52,8 @@ struct SystemData {
   ModelCfg cfg;
   float* psf = nullptr;
   float* psf_flip = nullptr;
+  uint4* psf_mfma = nullptr;  // Toeplitz fragments of the PSF (K <= kMfmaMaxK), else null
+  int psf_mfma_exp = 0;       // they hold psf 2^psf_mfma_exp
   float* obs = nullptr;
   int has_obs = 0;
   size_t bytes = 0;
@@ -72,6 +74,7 @@ int launch_conv(int K, const Group& g, size_t lds_bytes, hipStream_t st);
 int launch_subpix_adj(int key, const Group& g, hipStream_t st);
 int launch_finalize(const Group& g, hipStream_t st);
 size_t conv_lds_bytes(int H, int W, int K, int mode);
+constexpr size_t kConvLdsMax = 160 * 1024 - 256;  // dynamic LDS allowed to the PSF kernels
 
 // Block counts of one system per stage.
 inline int blocks_prologue(const SysDesc& s) { return s.P; }  // prologue, finalize

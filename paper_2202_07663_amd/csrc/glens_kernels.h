@@ -272,6 +272,262 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(Group g) {
 }
 
 // ------------------------------------------------------------------------------------------
+// PSF pass on matrix cores. One workgroup (4 waves) per particle. Each operand is scaled by a
+// power of two (exact) so that its largest magnitude lies in [2^14, 2^15), then split into two
+// fp16 parts, x = h + l with h = f16(x) and l = f16(x - h) (the difference is exact in FP32),
+// which represents it to about 2^-22 of itself: the scaled padded image sits in LDS as two
+// fp16 arrays, and the Toeplitz operands of the PSF are built (scaled and split) once per
+// model. Each output tile of 16 rows x N columns takes, for every PSF row a, three
+// v_mfma_f32_16x16x32_f16 accumulating in FP32 (hl + lh first, then hh; the dropped l.l term
+// is below 2^-22 of the product), and the result is scaled back. Against an FP64 sum this
+// keeps pixel errors near 6e-8, as an FP32 sum does. Operand layouts of the instruction (one
+// wave; lane l, element e): A[m][k] in lane m + 16 (k / 8), element k % 8; B[k][n] in lane
+// n + 16 (k / 8), element k % 8; D[m][n] in lane n + 16 (m / 4), element m % 4. Going from
+// PSF row a to a + 1 moves a tile's image rows down by one: lane (m, k / 8) takes the
+// fragment of lane (m + 1, k / 8) by a DPP row shift, and only the lanes with m = 15 read LDS.
+// Per pixel the likelihood and seed arithmetic is that of conv_kernel.
+// ------------------------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x -> two fp16 parts, stored at p[0], p[stride]
+__device__ __forceinline__ void split2_f16(float x, uint16_t* p, int stride) {
+  const _Float16 h = static_cast<_Float16>(x);
+  p[0] = __builtin_bit_cast(uint16_t, h);
+  p[stride] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(x - static_cast<float>(h)));
+}
+
+// Exponent s with max_abs 2^s in [2^14, 2^15) (0 for zero or non-finite values).
+__device__ __forceinline__ int f16_scale_exp(float max_abs) {
+  if (!(max_abs > 0.f) || !(max_abs < INFINITY)) return 0;
+  int e;
+  frexpf(max_abs, &e);  // max_abs = f 2^e, f in [0.5, 1)
+  return 15 - e;
+}
+
+// Largest value over the block, returned to every thread.
+__device__ __forceinline__ float block_max(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  float m = red[0];
+  for (int w = 1; w < nw; ++w) m = fmaxf(m, red[w]);
+  return m;
+}
+
+// Eight consecutive fp16 from LDS at an 8-byte aligned address.
+__device__ __forceinline__ f16x8 lds_frag(const uint16_t* p) {
+  const uint2 a = reinterpret_cast<const uint2*>(p)[0], b = reinterpret_cast<const uint2*>(p)[1];
+  return __builtin_bit_cast(f16x8, make_uint4(a.x, a.y, b.x, b.y));
+}
+
+// Lane i of each 16-lane row takes the fragment of lane i + 1 (DPP row_shl:1); lane 15 keeps
+// its own.
+__device__ __forceinline__ int dpp_row_next(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x101, 0xF, 0xF, false);
+}
+__device__ __forceinline__ f16x8 shift_rows(f16x8 f) {
+  int4 v = __builtin_bit_cast(int4, f);
+  v.x = dpp_row_next(v.x);
+  v.y = dpp_row_next(v.y);
+  v.z = dpp_row_next(v.z);
+  v.w = dpp_row_next(v.w);
+  return __builtin_bit_cast(f16x8, v);
+}
+
+__device__ __forceinline__ f32x4 mfma_f16(f16x8 a, f16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// acc[v] = correlation of the scaled LDS image (parts x, x + nel) with the scaled PSF over
+// the wave's tiles wave + 4 (U0 + v), v < G. tab: this direction's fragments [K][64][h, l];
+// those of row a + 1 are loaded while row a is computed. Each product is issued over the G
+// tiles before the next, so consecutive matrix instructions are independent.
+template <int U0, int G>
+__device__ __forceinline__ void mfma_tiles(const uint16_t* x, int nel, const MfmaGeom& q,
+                                           const uint4* __restrict__ tab, int K, int wave,
+                                           f32x4* acc) {
+  const int lane = threadIdx.x & 63, mr = lane & 15, g = lane >> 4;
+  int off[G];  // this lane's fragment offset in tile v at row a = 0
+  f16x8 ah[G], al[G];
+#pragma unroll
+  for (int v = 0; v < G; ++v) {
+    const int t = wave + 4 * (U0 + v);
+    const int tr = t / q.TC, tc = t - tr * q.TC;
+    off[v] = (tr * 16 + mr) * q.pitch + tc * q.N + 8 * g;
+    ah[v] = lds_frag(x + off[v]);
+    al[v] = lds_frag(x + off[v] + nel);
+    acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const uint4* tb = tab + lane * 2;
+  uint4 nh = tb[0], nl = tb[1];
+  for (int a = 0; a < K; ++a) {
+    const f16x8 bh = __builtin_bit_cast(f16x8, nh);
+    const f16x8 bl = __builtin_bit_cast(f16x8, nl);
+    if (a + 1 < K) {
+      tb += 64 * 2;
+      nh = tb[0];
+      nl = tb[1];
+    }
+#pragma unroll
+    for (int v = 0; v < G; ++v) acc[v] = mfma_f16(ah[v], bl, acc[v]);
+#pragma unroll
+    for (int v = 0; v < G; ++v) acc[v] = mfma_f16(al[v], bh, acc[v]);
+#pragma unroll
+    for (int v = 0; v < G; ++v) acc[v] = mfma_f16(ah[v], bh, acc[v]);
+    if (a + 1 < K) {
+#pragma unroll
+      for (int v = 0; v < G; ++v) {
+        ah[v] = shift_rows(ah[v]);
+        al[v] = shift_rows(al[v]);
+      }
+      if (mr == 15) {  // the new bottom row of each tile
+        const int ro = (a + 1) * q.pitch;
+#pragma unroll
+        for (int v = 0; v < G; ++v) {
+          ah[v] = lds_frag(x + off[v] + ro);
+          al[v] = lds_frag(x + off[v] + ro + nel);
+        }
+      }
+    }
+  }
+}
+
+// Per-pixel state of the matrix-core PSF kernel.
+struct MfmaPass {
+  const SysDesc& s;
+  const MfmaGeom& q;
+  int part, wave;
+  int unscale;  // exponent that takes the scaled sums back: -(image scale + PSF scale)
+  float* seed;  // LDS [H][W]
+  double ll, c2;
+};
+
+// Pixels of tiles wave + 4 (U0 + v), v < G: element r of acc[v] is pixel (i0 + r, j).
+// Forward (ADJ false): the model image, or the likelihood terms and the seed; adjoint: sbar.
+template <int U0, int G, bool ADJ>
+__device__ __forceinline__ void mfma_pixels(MfmaPass& P, const f32x4* acc) {
+  const SysDesc& s = P.s;
+  const int lane = threadIdx.x & 63, n = lane & 15, r0 = 4 * (lane >> 4);
+  const int H = s.H, W = s.W, HW = H * W;
+#pragma unroll
+  for (int v = 0; v < G; ++v) {
+    const int t = P.wave + 4 * (U0 + v), tr = t / P.q.TC, tc = t - tr * P.q.TC;
+    const int j = tc * P.q.N + n, i0 = tr * 16 + r0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + r;
+      if (n >= P.q.N || j >= W || i >= H) continue;
+      const float m = ldexpf(acc[v][r], P.unscale);
+      const size_t px = (size_t)P.part * HW + i * W + j;
+      if (ADJ) {
+        s.sbar[px] = m * s.inv_k2;
+      } else if (s.mode == 0) {
+        s.img[px] = m;
+      } else {
+        const float pos = m > 0.f ? m : 0.f;
+        const float s2 = s.s2b + pos * s.inv_gt;
+        const float res = s.obs[i * W + j] - m;
+        const float is2 = rcp_f32(s2);
+        const float chi = res * res * is2;
+        P.c2 += double(chi);
+        P.ll += double(chi + kLn2f * log2_f32(6.283185307179586f * s2));
+        const float sp = m > 0.f ? s.inv_gt : 0.f;
+        P.seed[i * W + j] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
+      }
+    }
+  }
+}
+
+// Tiles U0 .. U0 + 3 of the wave, as many as it has (ntw is wave-uniform): correlate, then
+// the per-pixel step.
+template <int U0, bool ADJ>
+__device__ __forceinline__ void mfma_group(MfmaPass& P, const uint16_t* x, int nel,
+                                           const uint4* tab, int ntw) {
+  const int r = ntw - U0, K = P.s.K;
+  f32x4 acc[4];
+  if (r >= 4) {
+    mfma_tiles<U0, 4>(x, nel, P.q, tab, K, P.wave, acc);
+    mfma_pixels<U0, 4, ADJ>(P, acc);
+  } else if (r == 3) {
+    mfma_tiles<U0, 3>(x, nel, P.q, tab, K, P.wave, acc);
+    mfma_pixels<U0, 3, ADJ>(P, acc);
+  } else if (r == 2) {
+    mfma_tiles<U0, 2>(x, nel, P.q, tab, K, P.wave, acc);
+    mfma_pixels<U0, 2, ADJ>(P, acc);
+  } else if (r == 1) {
+    mfma_tiles<U0, 1>(x, nel, P.q, tab, K, P.wave, acc);
+    mfma_pixels<U0, 1, ADJ>(P, acc);
+  }
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void mfma_pass(MfmaPass& P, const uint16_t* x, int nel,
+                                          const uint4* tab, int ntw) {
+  static_assert(kMfmaWaveTiles == 16, "four groups of four tiles");
+  mfma_group<0, ADJ>(P, x, nel, tab, ntw);
+  mfma_group<4, ADJ>(P, x, nel, tab, ntw);
+  mfma_group<8, ADJ>(P, x, nel, tab, ntw);
+  mfma_group<12, ADJ>(P, x, nel, tab, ntw);
+}
+
+__global__ void __launch_bounds__(kConvThreads) conv_mfma_kernel(Group g) {
+  extern __shared__ __align__(16) uint16_t xlds[];
+  __shared__ double red[kConvThreads / 64];
+  __shared__ float redf[kConvThreads / 64];
+  const int si = find_sys(g, blockIdx.x);
+  const SysDesc& s = g.sys[si];
+  const int part = blockIdx.x - g.block0[si];
+  const int H = s.H, W = s.W, HW = H * W, K = s.K, C = (K - 1) / 2, mode = s.mode;
+  const MfmaGeom q = mfma_geom(H, W, K);
+  const int nel = q.Hq * q.pitch;  // fp16 per part (a multiple of 8)
+  float* seed = reinterpret_cast<float*>(xlds + 2 * nel);
+  for (int i = threadIdx.x; i < nel / 4; i += blockDim.x)
+    reinterpret_cast<uint4*>(xlds)[i] = make_uint4(0u, 0u, 0u, 0u);
+  const float* m0 = s.m0 + (size_t)part * HW;
+  float mx = 0.f;
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) mx = fmaxf(mx, fabsf(m0[idx]));
+  const int sx = f16_scale_exp(block_max(mx, redf));  // its barriers also end the zero fill
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {  // coalesced global read
+    const int i = idx / W, j = idx - i * W;
+    split2_f16(ldexpf(m0[idx], sx), xlds + (i + C) * q.pitch + j + C, nel);
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  // tiles of this wave (wave-uniform: kept in a scalar register)
+  const int ntw = __builtin_amdgcn_readfirstlane(wave < q.T ? (q.T - wave + 3) / 4 : 0);
+  MfmaPass P{s, q, part, wave, -(sx + s.psf_mfma_exp), seed, 0.0, 0.0};
+  mfma_pass<false>(P, xlds, nel, s.psf_mfma, ntw);
+  if (mode == 0) return;
+  const double tot = block_sum(P.ll, red);
+  if (threadIdx.x == 0) {
+    const double v = -0.5 * tot;
+    s.logl[part] = isfinite(v) ? v : -INFINITY;
+  }
+  if (s.chi2) {
+    const double ctot = block_sum(P.c2, red);
+    if (threadIdx.x == 0) s.chi2[part] = ctot;
+  }
+  if (mode != 2) return;
+  // every wave is done with the image (block_max below starts with a barrier): its interior
+  // takes the scaled seed
+  mx = 0.f;
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) mx = fmaxf(mx, fabsf(seed[idx]));
+  const int ss = f16_scale_exp(block_max(mx, redf));
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {
+    const int i = idx / W, j = idx - i * W;
+    split2_f16(ldexpf(seed[idx], ss), xlds + (i + C) * q.pitch + j + C, nel);
+  }
+  __syncthreads();
+  // d logL / d m0 = correlation of the pixel seed with the (unflipped) PSF
+  P.unscale = -(ss + s.psf_mfma_exp);
+  mfma_pass<true>(P, xlds, nel, s.psf_mfma + 2 * 64 * K, ntw);
+}
+
+// ------------------------------------------------------------------------------------------
 // Banded PSF pass for small batches: one workgroup per (particle, band of rows), so that a
 // few particles still spread over many CUs. Band b owns output rows [b R_b, (b+1) R_b) and
 // loads the rows of its input it needs (C = (K-1)/2 more on either side). Three kernels:

@@ -1,6 +1,8 @@
 // Internal data layout shared by the host launchers and the HIP kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace glens {
@@ -105,6 +107,9 @@ struct SysDesc {
   const float* obs;
   const float* psf;      // K*K
   const float* psf_flip; // K*K, flipped in both axes
+  const uint4* psf_mfma; // [2][K][64 lanes][2 parts] Toeplitz fragments (flipped, plain)
+  int psf_mfma_exp;      // the fragments hold psf 2^psf_mfma_exp
+  int conv_mfma;         // 1: PSF pass on matrix cores
   const float* theta;    // [P][d] physical parameters, or null if z is given
   float* z;              // [P][d] unconstrained parameters (fit), or null
   const Prior* prior;    // [d] (fit)
@@ -126,6 +131,35 @@ struct SysDesc {
   float* seed;           // [P][H][W] adjoint seed (banded PSF pass)
   double* lpart;         // [P][max bands][2] log L and chi^2 partial sums per band
 };
+
+// PSF pass on matrix cores (v_mfma_f32_16x16x32_f16, operands scaled and split into two fp16
+// parts): for each PSF row a the output tile
+// [16 rows x N columns] += (image rows shifted by a, a 32-column window) x (the 32 x 16
+// Toeplitz matrix T_a[kk][n] = psf[a][kk - n]). N = min(16, 33 - K) columns fit the window.
+constexpr int kMfmaMaxK = 21;       // largest PSF for this pass
+constexpr int kMfmaWaveTiles = 16;  // output tiles per wave (4 waves: <= 64 tiles per image)
+
+struct MfmaGeom {
+  int N;       // useful output columns per tile
+  int TR, TC;  // tile rows / columns
+  int T;       // tiles
+  int Hq;      // rows of the padded image in LDS
+  int pitch;   // row pitch in 16-bit elements (a multiple of 4)
+};
+__host__ __device__ inline MfmaGeom mfma_geom(int H, int W, int K) {
+  MfmaGeom q;
+  q.N = 33 - K < 16 ? 33 - K : 16;
+  q.TR = (H + 15) / 16;
+  q.TC = (W + q.N - 1) / q.N;
+  q.T = q.TR * q.TC;
+  q.Hq = q.TR * 16 + K - 1;
+  q.pitch = ((q.TC - 1) * q.N + 32 + 3) & ~3;  // the last tile's 32-column window
+  return q;
+}
+// LDS bytes of the pass: the padded image as two fp16 parts, and the FP32 pixel seed.
+__host__ __device__ inline int mfma_lds_bytes(const MfmaGeom& q, int H, int W) {
+  return 4 * q.Hq * q.pitch + 4 * H * W;
+}
 
 constexpr int kMaxGroup = 10;
 constexpr int kConvMaxBands = 8;  // row bands per particle in the small-batch PSF pass
