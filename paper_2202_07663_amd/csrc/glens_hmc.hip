@@ -66,7 +66,7 @@ struct HmcArgs {
   float* T;            // trajectory length (device scalar)
   double* la;          // log T, Adam second moment, update count, averaged log T
   double* zbar;        // [2][d] chain means of the starts and of the proposals
-  float* cg;           // [C] ChEES gradient term of each chain
+  double* cg;          // [C] ChEES gradient term of each chain
 };
 
 __device__ __forceinline__ float step_size(const HmcArgs& a) {
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
         dot += s_w[j];
       }
       const double gc = (d1 - d0) * dot * a.u;
-      a.cg[c] = isfinite(gc) ? float(gc) : 0.f;
+      a.cg[c] = isfinite(gc) ? gc : 0.0;
     }
     const double h0 = -a.lps[c] + a.k0[c], h1 = -a.lp[c] + k1;
     double acc = exp(fmin(0.0, h0 - h1));
@@ -274,14 +274,17 @@ __global__ void hmc_adapt_kernel(HmcArgs a) {
   if (a.adapt_len && traj < a.n_adapt) {
     // ChEES: acceptance-weighted mean gradient w.r.t. T, then Adam (beta1 = 0, beta2 =
     // 0.95, rate 0.025) ascending in log T; the averaged log T uses the weights m^-kappa
+    // A chain with acceptance probability 0 has weight 0: it is left out, so that a far
+    // (rejected) proposal cannot turn the sum into 0 x inf.
     double num = 0.0, den = 0.0;
     for (int c = 0; c < a.C; ++c) {
+      if (!(a.accept[c] > 0.f)) continue;
       num += double(a.accept[c]) * a.cg[c];
       den += a.accept[c];
     }
-    if (den > 0.0) {
+    const double g = den > 0.0 ? num / den * exp(a.la[0]) : 0.0;
+    if (den > 0.0 && isfinite(g * g)) {
       const double m = a.la[2] + 1.0;
-      const double g = num / den * exp(a.la[0]);
       const double v = 0.95 * a.la[1] + 0.05 * g * g;
       const double vhat = v / (1.0 - pow(0.95, m));
       const double logT = a.la[0] + 0.025 * g / (sqrt(vhat) + 1e-8);
@@ -533,8 +536,8 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true);
   if (!rc) rc = fit_buffers_alloc(h->fb, C, d, pri.data());
   const size_t cd = size_t(C) * d;
-  const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 3 * C + 12) +
-                       sizeof(double) * (2 * cd + 3 * C + 12 + 2 * d) +
+  const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 2 * C + 12) +
+                       sizeof(double) * (2 * cd + 4 * C + 12 + 2 * d) +
                        sizeof(float) * size_t(o->n_samples) * cd + 256 * 24;
   if (!rc && hipMalloc(&h->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
   if (rc) {
@@ -579,7 +582,7 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   a.T = reinterpret_cast<float*>(take(sizeof(float) * 4));
   a.la = reinterpret_cast<double*>(take(sizeof(double) * 4));
   a.zbar = reinterpret_cast<double*>(take(sizeof(double) * 2 * d));
-  a.cg = reinterpret_cast<float*>(take(sizeof(float) * C));
+  a.cg = reinterpret_cast<double*>(take(sizeof(double) * C));
   a.adapt_len = o->adapt_length ? 1 : 0;
   h->max_leapfrog = o->max_leapfrog > 0 ? o->max_leapfrog : 1000;
   a.logl = m->ws.logl;

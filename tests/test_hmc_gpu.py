@@ -226,3 +226,25 @@ def test_trajectory_length_adaptation(G, sie40):
     assert abs(info["accept_mean"] - 0.95) < 0.05
     assert mean_err.max() < 0.15 and np.all(np.abs(sd_ratio - 1) < 0.12)
     assert dg.split_rhat(z).max() < 1.05
+
+
+def test_length_adaptation_survives_a_far_rejected_chain(G, sie40):
+    """The length gradient is an acceptance-weighted mean over chains. A chain started far
+    from the posterior makes proposals with a huge ChEES term and acceptance probability 0;
+    with weight 0 it must leave the adapted length and step size finite (in FP32 such a term
+    can overflow, and 0 x inf is NaN)."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    C = 32
+    rng = np.random.default_rng(5)
+    z0 = z_c + rng.normal(size=(C, z_c.size)) @ np.linalg.cholesky(cov).T
+    z0[3] = z_c + 1e6 * np.sqrt(np.diag(cov))  # a start 1e6 posterior widths away
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 5, 60, 10, priors, step_size=0.3, seed=17, inv_mass=cov,
+              z0=torch.from_numpy(z0).cuda(), adapt_length=True)
+    h.run()
+    info = h.info()
+    _say("far chain: T", info["trajectory_length"], "eps", info["step_size"], "accept",
+         info["accept_mean"])
+    assert np.isfinite(info["trajectory_length"]) and info["trajectory_length"] > 0
+    assert np.isfinite(info["step_size"]) and info["step_size"] > 0
+    assert np.all(np.isfinite(h.samples().cpu().numpy()[:, np.arange(C) != 3]))
