@@ -344,7 +344,7 @@ __device__ __forceinline__ f32x4 mfma_f16(f16x8 a, f16x8 b, f32x4 c) {
 
 // acc[v] = correlation of the scaled LDS image (parts x, x + nel) with the scaled PSF over
 // the wave's tiles wave + 4 (U0 + v), v < G. tab: this direction's fragments [K][64][h, l];
-// those of row a + 1 are loaded while row a is computed. Each product is issued over the G
+// those of row a + 2 are loaded while row a is computed. Each product is issued over the G
 // tiles before the next, so consecutive matrix instructions are independent.
 template <int U0, int G>
 __device__ __forceinline__ void mfma_tiles(const uint16_t* x, int nel, const MfmaGeom& q,
@@ -362,15 +362,21 @@ __device__ __forceinline__ void mfma_tiles(const uint16_t* x, int nel, const Mfm
     al[v] = lds_frag(x + off[v] + nel);
     acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
+  // PSF fragments two rows ahead (an L2 round trip is longer than one row's products)
   const uint4* tb = tab + lane * 2;
-  uint4 nh = tb[0], nl = tb[1];
+  uint4 nh = tb[0], nl = tb[1], nnh = nh, nnl = nl;
+  if (K > 1) {
+    nnh = tb[128];
+    nnl = tb[129];
+  }
   for (int a = 0; a < K; ++a) {
     const f16x8 bh = __builtin_bit_cast(f16x8, nh);
     const f16x8 bl = __builtin_bit_cast(f16x8, nl);
-    if (a + 1 < K) {
-      tb += 64 * 2;
-      nh = tb[0];
-      nl = tb[1];
+    nh = nnh;
+    nl = nnl;
+    if (a + 2 < K) {
+      nnh = tb[(a + 2) * 128];
+      nnl = tb[(a + 2) * 128 + 1];
     }
 #pragma unroll
     for (int v = 0; v < G; ++v) acc[v] = mfma_f16(ah[v], bl, acc[v]);
@@ -442,36 +448,42 @@ __device__ __forceinline__ void mfma_pixels(MfmaPass& P, const f32x4* acc) {
   }
 }
 
-// Tiles U0 .. U0 + 3 of the wave, as many as it has (ntw is wave-uniform): correlate, then
-// the per-pixel step.
-template <int U0, bool ADJ>
+// Tiles U0 .. U0 + G - 1 of the wave: correlate, then the per-pixel step.
+template <int U0, int G, bool ADJ>
 __device__ __forceinline__ void mfma_group(MfmaPass& P, const uint16_t* x, int nel,
-                                           const uint4* tab, int ntw) {
-  const int r = ntw - U0, K = P.s.K;
-  f32x4 acc[4];
-  if (r >= 4) {
-    mfma_tiles<U0, 4>(x, nel, P.q, tab, K, P.wave, acc);
-    mfma_pixels<U0, 4, ADJ>(P, acc);
-  } else if (r == 3) {
-    mfma_tiles<U0, 3>(x, nel, P.q, tab, K, P.wave, acc);
-    mfma_pixels<U0, 3, ADJ>(P, acc);
-  } else if (r == 2) {
-    mfma_tiles<U0, 2>(x, nel, P.q, tab, K, P.wave, acc);
-    mfma_pixels<U0, 2, ADJ>(P, acc);
-  } else if (r == 1) {
-    mfma_tiles<U0, 1>(x, nel, P.q, tab, K, P.wave, acc);
-    mfma_pixels<U0, 1, ADJ>(P, acc);
-  }
+                                           const uint4* tab) {
+  f32x4 acc[G];
+  mfma_tiles<U0, G>(x, nel, P.q, tab, P.s.K, P.wave, acc);
+  mfma_pixels<U0, G, ADJ>(P, acc);
 }
 
+// The wave's ntw tiles (wave-uniform) in groups of at most five, as even as possible: a
+// group's products hide the latency of the PSF fragment loads only when it has several tiles.
 template <bool ADJ>
 __device__ __forceinline__ void mfma_pass(MfmaPass& P, const uint16_t* x, int nel,
                                           const uint4* tab, int ntw) {
-  static_assert(kMfmaWaveTiles == 16, "four groups of four tiles");
-  mfma_group<0, ADJ>(P, x, nel, tab, ntw);
-  mfma_group<4, ADJ>(P, x, nel, tab, ntw);
-  mfma_group<8, ADJ>(P, x, nel, tab, ntw);
-  mfma_group<12, ADJ>(P, x, nel, tab, ntw);
+  static_assert(kMfmaWaveTiles == 16, "group table for up to 16 tiles");
+#define GL_G(U0, G) mfma_group<U0, G, ADJ>(P, x, nel, tab)
+  switch (ntw) {
+    case 1: GL_G(0, 1); break;
+    case 2: GL_G(0, 2); break;
+    case 3: GL_G(0, 3); break;
+    case 4: GL_G(0, 4); break;
+    case 5: GL_G(0, 5); break;
+    case 6: GL_G(0, 3); GL_G(3, 3); break;
+    case 7: GL_G(0, 4); GL_G(4, 3); break;
+    case 8: GL_G(0, 4); GL_G(4, 4); break;
+    case 9: GL_G(0, 5); GL_G(5, 4); break;
+    case 10: GL_G(0, 5); GL_G(5, 5); break;
+    case 11: GL_G(0, 4); GL_G(4, 4); GL_G(8, 3); break;
+    case 12: GL_G(0, 4); GL_G(4, 4); GL_G(8, 4); break;
+    case 13: GL_G(0, 5); GL_G(5, 4); GL_G(9, 4); break;
+    case 14: GL_G(0, 5); GL_G(5, 5); GL_G(10, 4); break;
+    case 15: GL_G(0, 5); GL_G(5, 5); GL_G(10, 5); break;
+    case 16: GL_G(0, 4); GL_G(4, 4); GL_G(8, 4); GL_G(12, 4); break;
+    default: break;
+  }
+#undef GL_G
 }
 
 __global__ void __launch_bounds__(kConvThreads) conv_mfma_kernel(Group g) {
@@ -487,13 +499,20 @@ __global__ void __launch_bounds__(kConvThreads) conv_mfma_kernel(Group g) {
   float* seed = reinterpret_cast<float*>(xlds + 2 * nel);
   for (int i = threadIdx.x; i < nel / 4; i += blockDim.x)
     reinterpret_cast<uint4*>(xlds)[i] = make_uint4(0u, 0u, 0u, 0u);
+  // the image goes through the (still unused) seed area: one coalesced pass over global
+  // memory with many loads in flight, its largest magnitude found on the way
   const float* m0 = s.m0 + (size_t)part * HW;
   float mx = 0.f;
-  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) mx = fmaxf(mx, fabsf(m0[idx]));
+#pragma unroll 8
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {
+    const float v = m0[idx];
+    seed[idx] = v;
+    mx = fmaxf(mx, fabsf(v));
+  }
   const int sx = f16_scale_exp(block_max(mx, redf));  // its barriers also end the zero fill
-  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {  // coalesced global read
+  for (int idx = threadIdx.x; idx < HW; idx += blockDim.x) {
     const int i = idx / W, j = idx - i * W;
-    split2_f16(ldexpf(m0[idx], sx), xlds + (i + C) * q.pitch + j + C, nel);
+    split2_f16(ldexpf(seed[idx], sx), xlds + (i + C) * q.pitch + j + C, nel);
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
