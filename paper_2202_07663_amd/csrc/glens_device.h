@@ -563,7 +563,7 @@ __host__ __device__ constexpr int shp_index(int n1, int n2) {
 // G = exp(-(u^2+v^2)/2), summed as U = sum_n1 g_n1(u) T_n1 with
 // T_n1 = sum_n2 c'_(n1,n2) g_n2(v).
 template <int NMAX>
-GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
+GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy, const float* shp) {
   const float u = sdx * c.inv_beta, v = sdy * c.inv_beta;
   float hu[NMAX + 1], hv[NMAX + 1];
   hermite<NMAX>(u, hu);
@@ -573,9 +573,9 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy) {
   float U = 0.f;
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1) {
-    float T = c.shp[shp_index(n1, 0)];
+    float T = shp[shp_index(n1, 0)];
 #pragma unroll
-    for (int n2 = 1; n2 <= NMAX - n1; ++n2) T = fmaf(c.shp[shp_index(n1, n2)], hv[n2], T);
+    for (int n2 = 1; n2 <= NMAX - n1; ++n2) T = fmaf(shp[shp_index(n1, n2)], hv[n2], T);
     U = n1 == 0 ? T : fmaf(hu[n1], T, U);
   }
   return exp2_f32(-0.5f * kLog2e * (u * u + v * v)) * U;

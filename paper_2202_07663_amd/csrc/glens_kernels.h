@@ -85,11 +85,11 @@ __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float
 
 template <int MASS, int LL, int NMAX>
 __device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
-                                                    double y) {
+                                                    double y, const float* shp) {
   MassState m;
   mass_eval<MASS, false>(c, s_c, nullptr, nullptr, x, y, m);
   float v = sersic_fwd(c.src, m.sdx, m.sdy);
-  if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy);
+  if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
   return v;
 }
@@ -103,6 +103,16 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
                                                const double* s_c, float* __restrict__ out,
                                                int p0, int p1) {
   const int W = s.W, k = s.k;
+  // shapelet coefficients held in vector registers for the whole loop (an empty asm with a
+  // vector-register operand): the scalar registers, which the compiler had filled, keep the
+  // other constants instead of reloading them every sub-pixel
+  constexpr int M = NMAX < 0 ? 1 : (NMAX + 1) * (NMAX + 2) / 2;
+  float shp[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    shp[q] = NMAX < 0 ? 0.f : c->shp[q];
+    asm("" : "+v"(shp[q]));
+  }
   for (int pix = p0 + threadIdx.x; pix < p1; pix += blockDim.x) {
     const int i = pix / W, j = pix - i * W;
     float sum = 0.f;
@@ -110,7 +120,7 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
       const double y = s.y0 + double(i * k + a) * s.dxs;
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
-        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y);
+        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, shp);
       }
     }
     out[pix] = sum * s.inv_k2;
