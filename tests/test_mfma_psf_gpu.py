@@ -76,3 +76,23 @@ def test_matrix_core_psf_pass(glens, case):
     err = np.abs(img[idx] - ref) / np.abs(ref).max(axis=(1, 2), keepdims=True)
     assert err.max() < 2e-5, err.max()
     m.close()
+
+
+def test_non_finite_vector_is_isolated_in_matrix_core_pass(glens):
+    """A NaN parameter vector in a 512-vector launch gets log L = -inf; the other vectors'
+    results are bitwise those of the same launch with a finite vector in its place (each
+    particle's image scale and sums are its own)."""
+    spec = synth.spec_c2()
+    from tests.helpers import load_workload
+    obs, truth = load_workload(spec.name)
+    theta = synth.draw_particles(spec, truth, P, seed=9)
+    m = glens.Model.from_spec(spec, obs)
+    ll_a, g_a = _run(m, theta)
+    bad = theta.copy()
+    bad[7, 0] = np.nan
+    ll_b, g_b = _run(m, bad)
+    keep = np.arange(P) != 7
+    assert ll_b[7] == -np.inf
+    np.testing.assert_array_equal(ll_a[keep], ll_b[keep])
+    np.testing.assert_array_equal(g_a[keep], g_b[keep])
+    m.close()
