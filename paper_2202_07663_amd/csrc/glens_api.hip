@@ -182,10 +182,13 @@ int choose_tiles(int P, int HW) {
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit) {
+int beta_per_particle(const ModelCfg& c) { return c.mass == 1 ? c.k * c.k * c.H * c.W : 0; }
+
+size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit, int beta_pp) {
   size_t b = align256(sizeof(PConst) * P) + 3 * align256(sizeof(float) * (size_t)P * HW) +
              align256(sizeof(double) * (size_t)P * tiles * kNAcc) +
-             align256(sizeof(double) * (size_t)P * kConvMaxBands * 2);
+             align256(sizeof(double) * (size_t)P * kConvMaxBands * 2) +
+             align256(sizeof(float2) * (size_t)P * beta_pp);
   if (fit) b += align256(sizeof(double) * P) + 2 * align256(sizeof(float) * (size_t)P * d);
   return b;
 }
@@ -195,15 +198,16 @@ void workspace_free(Workspace& ws) {
   ws = Workspace();
 }
 
-int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit) {
-  if (ws.pc && P <= ws.cap_P && tiles <= ws.cap_tiles && HW == ws.HW && (!fit || ws.logl))
+int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit, int beta_pp) {
+  if (ws.pc && P <= ws.cap_P && tiles <= ws.cap_tiles && HW == ws.HW && beta_pp == ws.beta_pp &&
+      (!fit || ws.logl))
     return GL_OK;
   const int cP = std::max(P, ws.cap_P), cT = std::max(tiles, ws.cap_tiles);
   if (ws.pc) {
     GL_HIP(hipDeviceSynchronize());
     workspace_free(ws);
   }
-  const size_t bytes = workspace_bytes(cP, cT, HW, d, fit);
+  const size_t bytes = workspace_bytes(cP, cT, HW, d, fit, beta_pp);
   char* base = nullptr;
   GL_HIP(hipMalloc(&base, bytes));
   size_t off = 0;
@@ -218,6 +222,9 @@ int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit) 
   ws.acc = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * cT * kNAcc));
   ws.seed = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
   ws.lpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * kConvMaxBands * 2));
+  ws.beta = beta_pp ? reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)cP * beta_pp))
+                    : nullptr;
+  ws.beta_pp = beta_pp;
   if (fit) {
     ws.logl = reinterpret_cast<double*>(take(sizeof(double) * cP));
     ws.grad = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
@@ -264,6 +271,7 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.sbar = ws.sbar;
   s.acc = ws.acc;
   s.seed = ws.seed;
+  s.beta = ws.beta;  // non-null exactly for EPL models
   s.lpart = ws.lpart;
   conv_bands(P, c.H, &s.bands, &s.band_rows);
   // matrix-core PSF pass for whole-image launches when the image's tiles and LDS fit; the
@@ -454,6 +462,7 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev
   set_blocks(g, blocks_prologue);
   if ((rc = launch_prologue(g, st))) return rc;
   GL_HIP(mark(1));
+  for (int i = 0; i < g.nsys; ++i) g.sys[i].mode = mode;  // the forward pass keeps beta in mode 2
   set_blocks(g, blocks_subpix);
   if ((rc = launch_subpix_fwd(key, g, st))) return rc;
   GL_HIP(mark(2));
@@ -547,7 +556,7 @@ static int run_model(gl_model* m, const float* theta, int P, int mode, float* im
   const ModelCfg& c = m->sys.cfg;
   const int HW = c.H * c.W;
   const int tiles = choose_tiles(P, HW);
-  int rc = workspace_reserve(m->ws, P, tiles, HW, c.d, false);
+  int rc = workspace_reserve(m->ws, P, tiles, HW, c.d, false, beta_per_particle(c));
   if (rc) return rc;
   Group g;
   std::memset(&g, 0, sizeof(g));

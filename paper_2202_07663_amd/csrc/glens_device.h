@@ -136,6 +136,10 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   c.e1f = float(e1);
   c.e2f = float(e2);
   c.lnb = float(log(B));
+  c.xcf = float(c.xc);
+  c.ycf = float(c.yc);
+  c.w2floorf = float(c.w2floor);
+  c.tlnb2 = float(c.tlnb * 1.4426950408889634);
   c.tfac = float(t / (2.0 * (1.0 - ee)));
   c.mj11 = float(j11);
   c.mj12 = float(j12);
@@ -174,6 +178,7 @@ GL_HD void series_step(int n, double t, double& ratio, double& dlog) {
 // of dc_n / dt = c_n sum_k dlog_k, given the running product and sum.
 GL_HD void series_store(PConst& c, int n, double cn, double dsum) {
   c.c[n] = n < c.nterms ? cn : 0.0;
+  c.cf[n] = n < c.nterms_d ? float(cn) : 0.f;
   c.dc[n] = n < c.nterms_d ? float(cn * dsum) : 0.f;
   if (n > 0) c.nc[n - 1] = n < c.nterms_d ? float(n * cn) : 0.f;
   if (n == kMaxTerms - 1) c.nc[kMaxTerms - 1] = 0.f;
@@ -457,6 +462,94 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     m.S = {float(Sr), float(Si)};
     m.alpha = {float(ar), float(ai)};
   }
+}
+
+// The EPL quantities the adjoint needs besides beta - x_s, in FP32: z, w, u2, X, ln|w|^2, A,
+// S, dS/dX, dS/dt, alpha. They only enter the Jacobian d(beta)/d(theta) and the local
+// derivatives, whose tolerance (a relative 1e-3 on the gradient) is far above FP32 rounding.
+// beta - x_s itself, at which the light profiles and their derivatives are evaluated, must
+// be the FP64 ray trace's (an FP32 one moves it by ~3e-7 arcsec, which shows at 2e-3 in the
+// gradient of a vector far from the posterior): the forward pass keeps it (SysDesc::beta)
+// and the caller sets m.sdx, m.sdy. The series run over the FP32-resolution length nterms_d;
+// log and exp are the hardware ones; dS/dX takes the closed form for |eps| >= kSxClosedMin
+// (its numerator cancels like |eps|, costing at most a relative 1e-7 / 0.02) and the series
+// below. cfs / ncs / dcs: the particle's c.cf / c.nc / c.dc (staged in LDS).
+__device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ cfs,
+                                                  const float* __restrict__ ncs,
+                                                  const float* __restrict__ dcs, double x,
+                                                  double y, MassState& m) {
+  const float zr = float(x) - c.xcf, zi = float(y) - c.ycf;
+  const float e1 = c.e1f, e2 = c.e2f;
+  const float wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
+  float w2 = wr * wr + wi * wi;
+  m.floored = w2 < c.w2floorf;
+  w2 = m.floored ? c.w2floorf : w2;
+  const float inv_w2 = rcp_f32(w2);
+  const float u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0f * wr * wi * inv_w2;
+  const float Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
+  const float l2w2 = log2_f32(w2);
+  // the value series, dS/dt and, for small |eps|, dS/dy by synthetic division (mass_eval)
+  const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
+  const bool sx_series = c.epsabs < kSxClosedMin;
+  const int nd4 = (c.nterms_d + 3) & ~3;
+  float b1 = 0.f, b2 = 0.f, d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
+  if (sx_series) {
+    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const int n = n0 + q;
+        const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
+        b2 = b1;
+        b1 = b0;
+        const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
+        d2 = d1;
+        d1 = d0;
+        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+        t2 = t1;
+        t1 = t0;
+      }
+    }
+  } else {
+    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const int n = n0 + q;
+        const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
+        b2 = b1;
+        b1 = b0;
+        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+        t2 = t1;
+        t1 = t0;
+      }
+    }
+  }
+  const float Sr = fmaf(-yr, b2, b1), Si = yi * b2;
+  float dr, di;  // dS/dy
+  if (sx_series) {
+    dr = fmaf(-yr, d2, d1);
+    di = yi * d2;
+  } else {
+    // X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S (see mass_eval)
+    const float xsr = Xr * Sr - Xi * Si, xsi = Xr * Si + Xi * Sr;
+    const float numr = c.hp * (1.0f - Sr) + c.hm * xsr;
+    const float numi = -c.hp * Si + c.hm * xsi;
+    const float denr = Xr + Xr * Xr - Xi * Xi, deni = Xi + 2.0f * Xr * Xi;
+    const float inv = rcp_f32(denr * denr + deni * deni);
+    dr = -(numr * denr + numi * deni) * inv;  // dS/dy = -dS/dX
+    di = -(numi * denr - numr * deni) * inv;
+  }
+  m.SX = {-dr, -di};  // d/dX = -d/dy
+  m.St = {fmaf(-yr, t2, t1), yi * t2};
+  // A = B^t |w|^-t = 2^(t log2 B - (t/2) log2 |w|^2)
+  const float A = exp2_f32(fmaf(-0.5f * c.tf, l2w2, c.tlnb2));
+  m.z = {zr, zi};
+  m.w = {wr, wi};
+  m.u2 = {u2r, u2i};
+  m.X = {Xr, Xi};
+  m.lnw2 = kLn2f * l2w2;
+  m.A = A;
+  m.S = {Sr, Si};
+  m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};
 }
 
 // Adds the mass-parameter terms of g . d(beta)/d(theta) to acc, with g = d s / d beta

@@ -286,7 +286,8 @@ int gl_fit_state_create(gl_model* m, const gl_fit_opts* o, gl_fit_state** out, v
   st->model = m;
   st->fp = fit_params(o);
   const ModelCfg& c = m->sys.cfg;
-  rc = workspace_reserve(m->ws, o->P, choose_tiles(o->P, c.H * c.W), c.H * c.W, c.d, true);
+  rc = workspace_reserve(m->ws, o->P, choose_tiles(o->P, c.H * c.W), c.H * c.W, c.d, true,
+                         beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(st->fb, o->P, c.d, pri.data());
   if (rc) {
     fit_buffers_free(st->fb);

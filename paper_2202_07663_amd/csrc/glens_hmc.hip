@@ -399,7 +399,7 @@ static int hmc_gradient(gl_hmc* h, float scale, int drift, hipStream_t st) {
   const ModelCfg& c = m->sys.cfg;
   const int tiles = choose_tiles(h->C, c.H * c.W);
   // Another call on the model may have regrown its workspace: reserve and re-read.
-  int rc = workspace_reserve(m->ws, h->C, tiles, c.H * c.W, c.d, true);
+  int rc = workspace_reserve(m->ws, h->C, tiles, c.H * c.W, c.d, true, beta_per_particle(c));
   if (rc) return rc;
   Group g;
   std::memset(&g, 0, sizeof(g));
@@ -533,7 +533,8 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   h->n_adapt = int(std::floor(double(o->adapt_frac) * o->n_burn));
   h->target = o->target_accept;
   hipStream_t st = (hipStream_t)stream;
-  rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true);
+  rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true,
+                         beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(h->fb, C, d, pri.data());
   const size_t cd = size_t(C) * d;
   const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 2 * C + 12) +

@@ -38,10 +38,14 @@ struct Workspace {
   float* theta = nullptr;  // internal theta (fits)
   float* seed = nullptr;   // adjoint seed of the banded PSF pass
   double* lpart = nullptr; // per-band likelihood partial sums
+  float2* beta = nullptr;  // beta - x_s per sub-pixel (EPL models)
+  int beta_pp = 0;         // its float2 entries per particle
   size_t bytes = 0;
 };
-size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit_buffers);
-int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit_buffers);
+// beta_pp: float2 entries of the beta buffer per particle (beta_per_particle(cfg)).
+size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit_buffers, int beta_pp);
+int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit_buffers,
+                      int beta_pp);
 void workspace_free(Workspace& ws);
 
 // Number of sub-pixel work tiles per particle for P particles of an H x W image.
@@ -65,6 +69,10 @@ void system_free(SystemData& sd);
 SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles);
 
 // Kernel configuration key of a system (systems with equal keys share launches).
+// Sub-pixel source offsets kept from the forward pass for the adjoint: k^2 H W per particle for
+// EPL models (whose adjoint takes its Jacobian in FP32 around them), none for SIE.
+int beta_per_particle(const ModelCfg& c);
+
 int subpix_key(const ModelCfg& c);  // (mass * 2 + lens_light) * 16 + (nmax + 1)
 
 // Launch stages over a group of systems (all with the same key / PSF size).

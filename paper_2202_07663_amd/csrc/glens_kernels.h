@@ -74,20 +74,22 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
 // ------------------------------------------------------------------------------------------
 // Copies the particle's series coefficients to LDS (read uniformly by every lane).
 __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float* s_nc,
-                                             float* s_dc) {
+                                             float* s_dc, float* s_cf = nullptr) {
   for (int n = threadIdx.x; n < kMaxTerms; n += blockDim.x) {
     s_c[n] = c.c[n];
     s_nc[n] = c.nc[n];
     s_dc[n] = c.dc[n];
+    if (s_cf) s_cf[n] = c.cf[n];
   }
   __syncthreads();
 }
 
 template <int MASS, int LL, int NMAX>
 __device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
-                                                    double y, const float* shp) {
+                                                    double y, const float* shp, float2& sd) {
   MassState m;
   mass_eval<MASS, false>(c, s_c, nullptr, nullptr, x, y, m);
+  sd = make_float2(m.sdx, m.sdy);
   float v = sersic_fwd(c.src, m.sdx, m.sdy);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
@@ -99,9 +101,10 @@ __device__ __forceinline__ float surface_brightness(const PConst& c, const doubl
 // The pixels [p0, p1) of one particle's model image. The restrict qualifiers tell the compiler
 // that the image stores do not write the particle's constants, which then stay scalar loads.
 template <int MASS, int LL, int NMAX>
+// beta (or null): where beta - x_s of each sub-pixel is kept for the adjoint, [k^2][H][W].
 __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* __restrict__ c,
                                                const double* s_c, float* __restrict__ out,
-                                               int p0, int p1) {
+                                               float2* __restrict__ beta, int p0, int p1) {
   const int W = s.W, k = s.k;
   // shapelet coefficients held in vector registers for the whole loop (an empty asm with a
   // vector-register operand): the scalar registers, which the compiler had filled, keep the
@@ -120,7 +123,9 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
       const double y = s.y0 + double(i * k + a) * s.dxs;
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
-        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, shp);
+        float2 sd;
+        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, shp, sd);
+        if (beta) beta[(a * k + b) * (s.H * W) + pix] = sd;
       }
     }
     out[pix] = sum * s.inv_k2;
@@ -140,7 +145,9 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int HW = s.H * s.W;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
-  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, p0, p1);
+  float2* beta = MASS == 1 && s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW
+                                                   : nullptr;
+  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, beta, p0, p1);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -767,8 +774,10 @@ subpix_adj_kernel(Group g) {
   const int part = lb / s.tiles, tile = lb - part * s.tiles;
   const PConst& c = s.pc[part];
   __shared__ double s_c[kMaxTerms];
-  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
-  stage_series(c, s_c, s_nc, s_dc);
+  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms], s_cf[kMaxTerms];
+  stage_series(c, s_c, s_nc, s_dc, s_cf);
+  // EPL: beta - x_s from the forward pass (kept there for gradient calls)
+  const float2* beta = MASS == 1 ? s.beta + (size_t)part * s.k * s.k * s.H * s.W : nullptr;
   const int HW = s.H * s.W, W = s.W, k = s.k;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
@@ -784,7 +793,14 @@ subpix_adj_kernel(Group g) {
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
         MassState m;
-        mass_eval<MASS, true>(c, s_c, s_nc, s_dc, x, y, m);
+        if (MASS == 1) {
+          const float2 sd = beta[(a * k + b) * HW + pix];
+          mass_jacobian_f32(c, s_cf, s_nc, s_dc, x, y, m);
+          m.sdx = sd.x;
+          m.sdy = sd.y;
+        } else {
+          mass_eval<MASS, true>(c, s_c, s_nc, s_dc, x, y, m);
+        }
         float gx, gy;
         sersic_adj(c.src, m.sdx, m.sdy, sb, acc + A_SRC, gx, gy);
         if (NMAX >= 0) {

@@ -67,7 +67,9 @@ static double request_work(const ModelCfg& c, int P) {
 
 static size_t request_bytes(const ModelCfg& c, int P) {
   const int HW = c.H * c.W;
-  return sizeof(float) * (2 * c.K * c.K + HW) + workspace_bytes(P, choose_tiles(P, HW), HW, c.d, true) +
+  const size_t psf_tab = c.K <= kMfmaMaxK ? size_t(2) * c.K * 64 * 16 * sizeof(uint16_t) : 0;
+  return sizeof(float) * (2 * c.K * c.K + HW) + psf_tab +
+         workspace_bytes(P, choose_tiles(P, HW), HW, c.d, true, beta_per_particle(c)) +
          fit_buffers_bytes(P, c.d);
 }
 
@@ -115,7 +117,7 @@ static int admit(gl_server* s, std::unique_ptr<Request> rq) {
   const int HW = c.H * c.W;
   a->tiles = choose_tiles(rq->fp.P, HW);
   int rc = system_upload(&rq->desc, c, a->sys);
-  if (!rc) rc = workspace_reserve(a->ws, rq->fp.P, a->tiles, HW, c.d, true);
+  if (!rc) rc = workspace_reserve(a->ws, rq->fp.P, a->tiles, HW, c.d, true, beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(a->fb, rq->fp.P, c.d, rq->priors.data());
   a->req = std::move(rq);
   if (rc) {

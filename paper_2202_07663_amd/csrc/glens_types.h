@@ -73,6 +73,9 @@ struct PConst {
   // FP32 part
   float theta_e, tf;   // Einstein radius, t
   float hp, hm;        // 1 - t/2, -t/2
+  float xcf, ycf;      // lens centre (FP32, adjoint Jacobian)
+  float w2floorf;      // R^2 floor on |w|^2 (FP32)
+  float tlnb2;         // t ln B log2(e)
   float e1f, e2f;
   float lnb;
   float tfac;          // t / (2 (1 - |eps|^2))
@@ -80,6 +83,7 @@ struct PConst {
   LightC lens, src;
   float beta, inv_beta;
   float shp[kMaxShp];  // c_k r_n1 r_n2 / (beta sqrt(pi)), r_n = sqrt(2^n / n!)
+  float cf[kMaxTerms]; // c_n in FP32 (zero from nterms_d on), for the adjoint's Jacobian
   float dc[kMaxTerms]; // d c_n / dt (zero from nterms_d on)
   float nc[kMaxTerms]; // (n + 1) c_{n+1}: coefficients of dS/dy (zero from nterms_d - 1 on)
 };
@@ -129,6 +133,7 @@ struct SysDesc {
   double* logl;          // [P]
   float* grad;           // [P][d]
   float* seed;           // [P][H][W] adjoint seed (banded PSF pass)
+  float2* beta;          // [P][k^2][H][W] beta - x_s of the forward pass (EPL, gradient calls)
   double* lpart;         // [P][max bands][2] log L and chi^2 partial sums per band
 };
 

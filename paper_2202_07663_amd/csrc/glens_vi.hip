@@ -220,7 +220,7 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
   gl_model* m = v->model;
   const ModelCfg& c = m->sys.cfg;
   const int tiles = choose_tiles(v->n, c.H * c.W);
-  int rc = workspace_reserve(m->ws, v->n, tiles, c.H * c.W, c.d, true);
+  int rc = workspace_reserve(m->ws, v->n, tiles, c.H * c.W, c.d, true, beta_per_particle(c));
   if (rc) return rc;
   ViArgs& a = v->a;
   a.k = v->k;
@@ -289,7 +289,8 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
   v->warmup = o->lr_warmup;
   v->lr_max = o->lr_max;
   hipStream_t st = (hipStream_t)stream;
-  rc = workspace_reserve(m->ws, n, choose_tiles(n, c.H * c.W), c.H * c.W, d, true);
+  rc = workspace_reserve(m->ws, n, choose_tiles(n, c.H * c.W), c.H * c.W, d, true,
+                         beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(v->fb, n, d, pri.data());
   const size_t nd = size_t(n) * d;
   const size_t bytes = sizeof(double) * (4 * size_t(nx) + nd + n + o->K) +
