@@ -182,7 +182,7 @@ int choose_tiles(int P, int HW) {
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-int beta_per_particle(const ModelCfg& c) { return c.mass == 1 ? c.k * c.k * c.H * c.W : 0; }
+int beta_per_particle(const ModelCfg& c) { return c.k * c.k * c.H * c.W; }
 
 size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit, int beta_pp) {
   size_t b = align256(sizeof(PConst) * P) + 3 * align256(sizeof(float) * (size_t)P * HW) +
@@ -271,7 +271,7 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.sbar = ws.sbar;
   s.acc = ws.acc;
   s.seed = ws.seed;
-  s.beta = ws.beta;  // non-null exactly for EPL models
+  s.beta = ws.beta;
   s.lpart = ws.lpart;
   conv_bands(P, c.H, &s.bands, &s.band_rows);
   // matrix-core PSF pass for whole-image launches when the image's tiles and LDS fit; the

@@ -140,6 +140,7 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   c.ycf = float(c.yc);
   c.w2floorf = float(c.w2floor);
   c.tlnb2 = float(c.tlnb * 1.4426950408889634);
+  c.bmassf = float(B);
   c.tfac = float(t / (2.0 * (1.0 - ee)));
   c.mj11 = float(j11);
   c.mj12 = float(j12);
@@ -164,6 +165,9 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   } else {
     c.sr = c.si = 0.0;
   }
+  c.srf = float(c.sr);
+  c.sif = float(c.si);
+  c.inv_epsabsf = eabs > 0.0 ? float(1.0 / eabs) : 0.f;
 }
 
 // Series ratio c_n / c_{n-1} = (2n - 2 + t) / (2n + 2 - t) and the increment of
@@ -464,7 +468,7 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
   }
 }
 
-// The EPL quantities the adjoint needs besides beta - x_s, in FP32: z, w, u2, X, ln|w|^2, A,
+// The lens quantities the adjoint needs besides beta - x_s, in FP32: z, w, u2, X, ln|w|^2, A,
 // S, dS/dX, dS/dt, alpha. They only enter the Jacobian d(beta)/d(theta) and the local
 // derivatives, whose tolerance (a relative 1e-3 on the gradient) is far above FP32 rounding.
 // beta - x_s itself, at which the light profiles and their derivatives are evaluated, must
@@ -474,6 +478,7 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
 // log and exp are the hardware ones; dS/dX takes the closed form for |eps| >= kSxClosedMin
 // (its numerator cancels like |eps|, costing at most a relative 1e-7 / 0.02) and the series
 // below. cfs / ncs / dcs: the particle's c.cf / c.nc / c.dc (staged in LDS).
+template <int MASS>
 __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ cfs,
                                                   const float* __restrict__ ncs,
                                                   const float* __restrict__ dcs, double x,
@@ -488,6 +493,32 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   const float u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0f * wr * wi * inv_w2;
   const float Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
   const float l2w2 = log2_f32(w2);
+  m.z = {zr, zi};
+  m.w = {wr, wi};
+  m.u2 = {u2r, u2i};
+  m.X = {Xr, Xi};
+  m.lnw2 = kLn2f * l2w2;
+  if (MASS == 0 && c.sie_closed) {
+    // SIE, |eps| >= kSieClosedMin: S = atan(zeta) conj(zeta) / |eps|, zeta = s w / |w|, as in
+    // mass_eval; dS/dX = (1/(1+X) - S) / (2X) (|X| = |eps| >= 0.1: no cancellation to fear)
+    const float rinv = __builtin_amdgcn_rsqf(w2);
+    const float ur = wr * rinv, ui = wi * rinv;
+    const float a = c.srf * ur - c.sif * ui, b = c.srf * ui + c.sif * ur, aa = a * a;
+    const float atr = 0.5f * atanf(2.0f * a / (1.0f - float(c.epsabs)));
+    const float ati = 0.25f * kLn2f *
+                      (log2_f32((1.0f + b) * (1.0f + b) + aa) - log2_f32((1.0f - b) * (1.0f - b) + aa));
+    const float Sr = (atr * a + ati * b) * c.inv_epsabsf, Si = (ati * a - atr * b) * c.inv_epsabsf;
+    const float opr = 1.0f + Xr, opi = Xi, dd = rcp_f32(opr * opr + opi * opi);
+    const float nr = opr * dd - Sr, ni = -opi * dd - Si;
+    const float hx = 0.5f * rcp_f32(Xr * Xr + Xi * Xi);
+    m.SX = {(nr * Xr + ni * Xi) * hx, (ni * Xr - nr * Xi) * hx};
+    m.St = {0.f, 0.f};
+    const float A = c.bmassf * rinv;
+    m.A = A;
+    m.S = {Sr, Si};
+    m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};
+    return;
+  }
   // the value series, dS/dt and, for small |eps|, dS/dy by synthetic division (mass_eval)
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
   const bool sx_series = c.epsabs < kSxClosedMin;
@@ -542,11 +573,6 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   m.St = {fmaf(-yr, t2, t1), yi * t2};
   // A = B^t |w|^-t = 2^(t log2 B - (t/2) log2 |w|^2)
   const float A = exp2_f32(fmaf(-0.5f * c.tf, l2w2, c.tlnb2));
-  m.z = {zr, zi};
-  m.w = {wr, wi};
-  m.u2 = {u2r, u2i};
-  m.X = {Xr, Xi};
-  m.lnw2 = kLn2f * l2w2;
   m.A = A;
   m.S = {Sr, Si};
   m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};

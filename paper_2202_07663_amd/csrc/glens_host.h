@@ -38,7 +38,7 @@ struct Workspace {
   float* theta = nullptr;  // internal theta (fits)
   float* seed = nullptr;   // adjoint seed of the banded PSF pass
   double* lpart = nullptr; // per-band likelihood partial sums
-  float2* beta = nullptr;  // beta - x_s per sub-pixel (EPL models)
+  float2* beta = nullptr;  // beta - x_s per sub-pixel, from the forward pass
   int beta_pp = 0;         // its float2 entries per particle
   size_t bytes = 0;
 };
@@ -69,8 +69,8 @@ void system_free(SystemData& sd);
 SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles);
 
 // Kernel configuration key of a system (systems with equal keys share launches).
-// Sub-pixel source offsets kept from the forward pass for the adjoint: k^2 H W per particle for
-// EPL models (whose adjoint takes its Jacobian in FP32 around them), none for SIE.
+// Sub-pixel source offsets kept from the forward pass for the adjoint (which takes the lens
+// Jacobian in FP32 around them): k^2 H W per particle.
 int beta_per_particle(const ModelCfg& c);
 
 int subpix_key(const ModelCfg& c);  // (mass * 2 + lens_light) * 16 + (nmax + 1)

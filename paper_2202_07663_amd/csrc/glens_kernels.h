@@ -145,8 +145,7 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int HW = s.H * s.W;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
-  float2* beta = MASS == 1 && s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW
-                                                   : nullptr;
+  float2* beta = s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW : nullptr;
   forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, beta, p0, p1);
 }
 
@@ -776,8 +775,8 @@ subpix_adj_kernel(Group g) {
   __shared__ double s_c[kMaxTerms];
   __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms], s_cf[kMaxTerms];
   stage_series(c, s_c, s_nc, s_dc, s_cf);
-  // EPL: beta - x_s from the forward pass (kept there for gradient calls)
-  const float2* beta = MASS == 1 ? s.beta + (size_t)part * s.k * s.k * s.H * s.W : nullptr;
+  // beta - x_s from the forward pass (kept there for gradient calls)
+  const float2* beta = s.beta + (size_t)part * s.k * s.k * s.H * s.W;
   const int HW = s.H * s.W, W = s.W, k = s.k;
   const int p0 = tile * s.pix_per_tile;
   const int p1 = min(HW, p0 + s.pix_per_tile);
@@ -793,14 +792,10 @@ subpix_adj_kernel(Group g) {
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
         MassState m;
-        if (MASS == 1) {
-          const float2 sd = beta[(a * k + b) * HW + pix];
-          mass_jacobian_f32(c, s_cf, s_nc, s_dc, x, y, m);
-          m.sdx = sd.x;
-          m.sdy = sd.y;
-        } else {
-          mass_eval<MASS, true>(c, s_c, s_nc, s_dc, x, y, m);
-        }
+        const float2 sd = beta[(a * k + b) * HW + pix];
+        mass_jacobian_f32<MASS>(c, s_cf, s_nc, s_dc, x, y, m);
+        m.sdx = sd.x;
+        m.sdy = sd.y;
         float gx, gy;
         sersic_adj(c.src, m.sdx, m.sdy, sb, acc + A_SRC, gx, gy);
         if (NMAX >= 0) {

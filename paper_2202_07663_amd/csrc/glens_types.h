@@ -76,6 +76,7 @@ struct PConst {
   float xcf, ycf;      // lens centre (FP32, adjoint Jacobian)
   float w2floorf;      // R^2 floor on |w|^2 (FP32)
   float tlnb2;         // t ln B log2(e)
+  float srf, sif, bmassf, inv_epsabsf;  // SIE closed form in FP32 (adjoint Jacobian)
   float e1f, e2f;
   float lnb;
   float tfac;          // t / (2 (1 - |eps|^2))
@@ -133,7 +134,7 @@ struct SysDesc {
   double* logl;          // [P]
   float* grad;           // [P][d]
   float* seed;           // [P][H][W] adjoint seed (banded PSF pass)
-  float2* beta;          // [P][k^2][H][W] beta - x_s of the forward pass (EPL, gradient calls)
+  float2* beta;          // [P][k^2][H][W] beta - x_s of the forward pass (gradient calls)
   double* lpart;         // [P][max bands][2] log L and chi^2 partial sums per band
 };
 

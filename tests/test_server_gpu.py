@@ -73,17 +73,18 @@ def test_server_matches_gl_fit(G):
 
 
 def test_small_budget_forces_queueing(G):
-    """A budget that holds one of these systems at a time: everything still completes, in
-    order, and device memory in use never exceeds the budget."""
+    """A budget that holds one of these systems at a time (a request here is ~20 MB, most of it
+    the sub-pixel source offsets the adjoint reuses): everything still completes, in order,
+    and device memory in use never exceeds the budget."""
     case = MIX[0]
-    srv = G.Server(hbm_budget_bytes=8 << 20, max_systems=8, steps_per_tick=4,
+    srv = G.Server(hbm_budget_bytes=32 << 20, max_systems=8, steps_per_tick=4,
                    fill_subpixels=1e12)
     tickets = [_submit(srv, case, K=8, seed=i) for i in range(4)]
     res = [srv.wait(t) for t in tickets]
     st = srv.stats()
     srv.close()
     assert all(r["status"] == 0 for r in res)
-    assert st["hbm_peak"] <= 8 << 20
+    assert st["hbm_peak"] <= 32 << 20
     admits = [r["t_admit"] for r in res]
     dones = [r["t_done"] for r in res]
     assert admits == sorted(admits)
