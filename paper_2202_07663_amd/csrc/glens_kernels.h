@@ -125,7 +125,11 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
         const double x = s.x0 + double(j * k + b) * s.dxs;
         float2 sd;
         sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, shp, sd);
-        if (beta) beta[(a * k + b) * (s.H * W) + pix] = sd;
+        if (beta) {  // streamed past the caches: read once, by the adjoint, much later
+          float* bp = reinterpret_cast<float*>(beta + (a * k + b) * (s.H * W) + pix);
+          __builtin_nontemporal_store(sd.x, bp);
+          __builtin_nontemporal_store(sd.y, bp + 1);
+        }
       }
     }
     out[pix] = sum * s.inv_k2;
@@ -792,7 +796,9 @@ subpix_adj_kernel(Group g) {
       for (int b = 0; b < k; ++b) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
         MassState m;
-        const float2 sd = beta[(a * k + b) * HW + pix];
+        const float* bp = reinterpret_cast<const float*>(beta + (a * k + b) * HW + pix);
+        const float2 sd =
+            make_float2(__builtin_nontemporal_load(bp), __builtin_nontemporal_load(bp + 1));
         mass_jacobian_f32<MASS>(c, s_cf, s_nc, s_dc, x, y, m);
         m.sdx = sd.x;
         m.sdy = sd.y;
