@@ -312,7 +312,7 @@ GL_HD Cx cconj(Cx a) { return {a.r, -a.i}; }
 GL_HD Cx cmuli(Cx a) { return {-a.i, a.r}; }  // i a
 GL_HD float cdot(Cx g, Cx v) { return g.r * v.r + g.i * v.i; }  // real dot product
 
-// Ray trace of one sub-pixel; the FP32 fields are kept for the adjoint.
+// The lens quantities of one sub-pixel that the adjoint uses (FP32).
 struct MassState {
   float sdx, sdy;     // beta - x_s (source offset)
   Cx z, w, u2, X;     // z, w, w^2/|w|^2, X = conj(eps) u2
@@ -323,23 +323,20 @@ struct MassState {
   int floored;        // |w|^2 hit the floor
 };
 
-// EPL / SIE deflection plus shear at image position (x, y); beta = x - alpha - alpha_ext.
-// ADJ: also dS/dX and dS/dt (FP32). cs / ncs / dcs: the particle's coefficient tables
-// c.c / c.nc / c.dc (the kernels pass copies staged in LDS).
-template <int MASS, bool ADJ>
-GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
-                     const float* __restrict__ ncs, const float* __restrict__ dcs, double x,
-                     double y, MassState& m) {
+// EPL / SIE deflection plus shear at image position (x, y), in FP64: returns beta - x_s with
+// beta = x - alpha - alpha_ext. cs: the particle's series coefficients c.c (the kernels pass
+// a copy staged in LDS).
+template <int MASS>
+GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, double y,
+                     float& sdx, float& sdy) {
   const double zr = x - c.xc, zi = y - c.yc;
   const double e1 = c.e1, e2 = c.e2;
   const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
   double w2 = wr * wr + wi * wi;
-  m.floored = w2 < c.w2floor;
-  w2 = m.floored ? c.w2floor : w2;
+  w2 = w2 < c.w2floor ? c.w2floor : w2;
   const double inv_w2 = rcp_f64(w2);
   const double u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0 * wr * wi * inv_w2;
   const double Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
-  const double lnw2 = log_f64(w2);
   double Sr, Si, A;
   if (MASS == 0 && c.sie_closed) {
     // S_1(X) = atan(zeta) / zeta, zeta = s w / |w|; atan of |zeta| < 1 in closed form
@@ -353,35 +350,20 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
     Sr = (atr * a + ati * b) * ie;
     Si = (ati * a - atr * b) * ie;
     A = c.bmass * rinv;
-    if (ADJ) {
-      // S_X = (1/(1+X) - S) / (2X), in double: cancels for small |X|
-      const double opr = 1.0 + Xr, opi = Xi, d = 1.0 / (opr * opr + opi * opi);
-      const double nr = opr * d - Sr, ni = -opi * d - Si;
-      const double dx = 0.5 / (Xr * Xr + Xi * Xi);
-      m.SX = {float((nr * Xr + ni * Xi) * dx), float((ni * Xr - nr * Xi) * dx)};
-      m.St = {0.f, 0.f};
-    }
   } else {
-    const double yr = -Xr, yi = -Xi;
-    // The coefficients are real, so each series is evaluated at the complex point y by
+    // The coefficients are real, so the series is evaluated at the complex point y = -X by
     // synthetic division by the real quadratic (v - y)(v - conj y) = v^2 - 2 Re(y) v + |y|^2
     // (Knuth, TAOCP vol. 2, sec. 4.6.4): b_n = c_n + 2 Re(y) b_(n+1) - |y|^2 b_(n+2) from the
     // top down to n = 0, and the sum is b_0 - Re(y) b_1 + i Im(y) b_1. That is two real FMAs
     // per term where complex Horner takes four. |y| = |eps| < 1, so rounding errors made
-    // early are damped as the recurrence runs down.
-    // Terms are taken four per trip; coefficients past the series lengths are zero, so
-    // rounding the lengths up to a multiple of four is exact. The value series
-    // S(y) = sum c_n y^n runs in FP64 over all terms; the adjoint's derivative series
-    // S'(y) = sum (n+1) c_(n+1) y^n and dS/dt = sum dc_n y^n run in FP32 over the first
-    // nterms_d terms only.
+    // early are damped as the recurrence runs down. Terms are taken four per trip;
+    // coefficients past the series length are zero, so rounding the length up to a multiple
+    // of four is exact.
+    const double yr = -Xr, yi = -Xi;
     const double r2 = 2.0 * yr, yy = fma(yr, yr, yi * yi);
     double b1 = 0.0, b2 = 0.0;  // b_(n+1), b_(n+2)
     const int nt4 = (c.nterms + 3) & ~3;
-    // dS/dX: by its series only for small |eps|; otherwise from S below. dS/dt (EPL): always
-    // by its series.
-    const bool sx_series = ADJ && c.epsabs < kSxClosedMin;
-    const int nd4 = (ADJ && (MASS == 1 || sx_series)) ? ((c.nterms_d + 3) & ~3) : 0;
-    for (int n0 = nt4 - 4; n0 >= nd4; n0 -= 4) {
+    for (int n0 = nt4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
         const double b0 = fma(r2, b1, fma(-yy, b2, cs[n0 + q]));
@@ -389,83 +371,14 @@ GL_HD void mass_eval(const PConst& c, const double* __restrict__ cs,
         b1 = b0;
       }
     }
-    if (ADJ) {
-      const float r2f = float(r2), yyf = float(yy);
-      float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
-      if (sx_series) {
-        for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-          for (int q = 3; q >= 0; --q) {
-            const int n = n0 + q;
-            const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
-            b2 = b1;
-            b1 = b0;
-            const float d0 = fmaf(r2f, d1, fmaf(-yyf, d2, ncs[n]));
-            d2 = d1;
-            d1 = d0;
-            if (MASS == 1) {
-              const float t0 = fmaf(r2f, t1, fmaf(-yyf, t2, dcs[n]));
-              t2 = t1;
-              t1 = t0;
-            }
-          }
-        }
-      } else {
-        for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-          for (int q = 3; q >= 0; --q) {
-            const int n = n0 + q;
-            const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
-            b2 = b1;
-            b1 = b0;
-            const float t0 = fmaf(r2f, t1, fmaf(-yyf, t2, dcs[n]));
-            t2 = t1;
-            t1 = t0;
-          }
-        }
-      }
-      const float yrf = float(yr), yif = float(yi);
-      const float tr = fmaf(-yrf, t2, t1), ti = yif * t2;
-      float dr, di;
-      if (sx_series) {
-        dr = fmaf(-yrf, d2, d1);
-        di = yif * d2;
-      } else {
-        // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
-        //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S,
-        // (as series: the coefficient of (-X)^n on both sides agrees for every n). The
-        // numerator cancels like |X| = |eps|, so it is formed in FP64 from the FP64 S.
-        const double sr = fma(-yr, b2, b1), si = yi * b2;
-        const double h = 0.5 * c.t;
-        const double xsr = Xr * sr - Xi * si, xsi = Xr * si + Xi * sr;
-        const float numr = float((1.0 - h) * (1.0 - sr) - h * xsr);
-        const float numi = float(-(1.0 - h) * si - h * xsi);
-        const float denr = float(Xr + Xr * Xr - Xi * Xi), deni = float(Xi + 2.0 * Xr * Xi);
-        const float inv = rcp_f32(denr * denr + deni * deni);
-        dr = -(numr * denr + numi * deni) * inv;  // dS/dy = -dS/dX
-        di = -(numi * denr - numr * deni) * inv;
-      }
-      m.SX = {-dr, -di};  // d/dX = -d/dy
-      m.St = {tr, ti};
-    }
     Sr = fma(-yr, b2, b1);
     Si = yi * b2;
-    A = exp_f64(c.tlnb - 0.5 * c.t * lnw2);
+    A = exp_f64(c.tlnb - 0.5 * c.t * log_f64(w2));
   }
   const double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
   // beta - x_s = x - alpha - alpha_ext - x_s
-  m.sdx = float(x - ar - (c.g1 * x + c.g2 * y) - c.sxs);
-  m.sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
-  if (ADJ) {
-    m.z = {float(zr), float(zi)};
-    m.w = {float(wr), float(wi)};
-    m.u2 = {float(u2r), float(u2i)};
-    m.X = {float(Xr), float(Xi)};
-    m.lnw2 = float(lnw2);
-    m.A = float(A);
-    m.S = {float(Sr), float(Si)};
-    m.alpha = {float(ar), float(ai)};
-  }
+  sdx = float(x - ar - (c.g1 * x + c.g2 * y) - c.sxs);
+  sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
 }
 
 // The lens quantities the adjoint needs besides beta - x_s, in FP32: z, w, u2, X, ln|w|^2, A,
@@ -500,7 +413,7 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   m.lnw2 = kLn2f * l2w2;
   if (MASS == 0 && c.sie_closed) {
     // SIE, |eps| >= kSieClosedMin: S = atan(zeta) conj(zeta) / |eps|, zeta = s w / |w|, as in
-    // mass_eval; dS/dX = (1/(1+X) - S) / (2X) (|X| = |eps| >= 0.1: no cancellation to fear)
+    // ray_trace; dS/dX = (1/(1+X) - S) / (2X) (|X| = |eps| >= 0.1: no cancellation to fear)
     const float rinv = __builtin_amdgcn_rsqf(w2);
     const float ur = wr * rinv, ui = wi * rinv;
     const float a = c.srf * ur - c.sif * ui, b = c.srf * ui + c.sif * ur, aa = a * a;
@@ -519,7 +432,7 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
     m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};
     return;
   }
-  // the value series, dS/dt and, for small |eps|, dS/dy by synthetic division (mass_eval)
+  // the value series, dS/dt and, for small |eps|, dS/dy by synthetic division (ray_trace)
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
   const bool sx_series = c.epsabs < kSxClosedMin;
   const int nd4 = (c.nterms_d + 3) & ~3;
@@ -560,7 +473,10 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
     dr = fmaf(-yr, d2, d1);
     di = yi * d2;
   } else {
-    // X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S (see mass_eval)
+    // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
+    //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S
+    // (as series: the coefficient of (-X)^n on both sides agrees for every n). The numerator
+    // cancels like |X| = |eps|, so this is used for |eps| >= kSxClosedMin only.
     const float xsr = Xr * Sr - Xi * Si, xsi = Xr * Si + Xi * Sr;
     const float numr = c.hp * (1.0f - Sr) + c.hm * xsr;
     const float numi = -c.hp * Si + c.hm * xsi;

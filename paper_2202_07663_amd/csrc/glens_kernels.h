@@ -87,11 +87,9 @@ __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float
 template <int MASS, int LL, int NMAX>
 __device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
                                                     double y, const float* shp, float2& sd) {
-  MassState m;
-  mass_eval<MASS, false>(c, s_c, nullptr, nullptr, x, y, m);
-  sd = make_float2(m.sdx, m.sdy);
-  float v = sersic_fwd(c.src, m.sdx, m.sdy);
-  if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy, shp);
+  ray_trace<MASS>(c, s_c, x, y, sd.x, sd.y);
+  float v = sersic_fwd(c.src, sd.x, sd.y);
+  if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, sd.x, sd.y, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
   return v;
 }
