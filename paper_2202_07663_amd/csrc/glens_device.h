@@ -381,21 +381,25 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, d
   sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
 }
 
-// The lens quantities the adjoint needs besides beta - x_s, in FP32: z, w, u2, X, ln|w|^2, A,
-// S, dS/dX, dS/dt, alpha. They only enter the Jacobian d(beta)/d(theta) and the local
-// derivatives, whose tolerance (a relative 1e-3 on the gradient) is far above FP32 rounding.
-// beta - x_s itself, at which the light profiles and their derivatives are evaluated, must
-// be the FP64 ray trace's (an FP32 one moves it by ~3e-7 arcsec, which shows at 2e-3 in the
-// gradient of a vector far from the posterior): the forward pass keeps it (SysDesc::beta)
-// and the caller sets m.sdx, m.sdy. The series run over the FP32-resolution length nterms_d;
-// log and exp are the hardware ones; dS/dX takes the closed form for |eps| >= kSxClosedMin
-// (its numerator cancels like |eps|, costing at most a relative 1e-7 / 0.02) and the series
-// below. cfs / ncs / dcs: the particle's c.cf / c.nc / c.dc (staged in LDS).
+// The lens quantities the adjoint needs, in FP32: z, w, u2, X, ln|w|^2, A, S, dS/dX, dS/dt,
+// alpha. (sdx, sdy) is beta - x_s of the forward pass's FP64 ray trace (SysDesc::beta): the
+// light profiles and their derivatives are evaluated there (an FP32 ray trace moves it by
+// ~3e-7 arcsec, which shows at 2e-3 in the gradient of a vector far from the posterior). The
+// rest only enters the Jacobian d(beta)/d(theta) and the local derivatives, whose tolerance
+// (a relative 1e-3 on the gradient) is far above FP32 rounding:
+//   alpha = x - alpha_ext - x_s - (beta - x_s), formed from the kept offset (FP64 up to the
+//         last subtraction), and S = alpha / (A w), so the value series is not run again
+//         (a sub-pixel whose |w|^2 hit the floor, where alpha carries no S, sums it);
+//   dS/dX by the closed form of the identity below for |eps| >= kSxClosedMin (its numerator
+//         cancels like |eps|, costing at most a relative 1e-6 / 0.02), by its series below;
+//   dS/dt (EPL) by its series; the series run over the FP32-resolution length nterms_d;
+//   log and exp are the hardware ones.
+// cfs / ncs / dcs: the particle's c.cf / c.nc / c.dc (staged in LDS).
 template <int MASS>
 __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ cfs,
                                                   const float* __restrict__ ncs,
                                                   const float* __restrict__ dcs, double x,
-                                                  double y, MassState& m) {
+                                                  double y, float sdx, float sdy, MassState& m) {
   const float zr = float(x) - c.xcf, zi = float(y) - c.ycf;
   const float e1 = c.e1f, e2 = c.e2f;
   const float wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
@@ -406,68 +410,64 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   const float u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0f * wr * wi * inv_w2;
   const float Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
   const float l2w2 = log2_f32(w2);
+  m.sdx = sdx;
+  m.sdy = sdy;
   m.z = {zr, zi};
   m.w = {wr, wi};
   m.u2 = {u2r, u2i};
   m.X = {Xr, Xi};
   m.lnw2 = kLn2f * l2w2;
-  if (MASS == 0 && c.sie_closed) {
-    // SIE, |eps| >= kSieClosedMin: S = atan(zeta) conj(zeta) / |eps|, zeta = s w / |w|, as in
-    // ray_trace; dS/dX = (1/(1+X) - S) / (2X) (|X| = |eps| >= 0.1: no cancellation to fear)
-    const float rinv = __builtin_amdgcn_rsqf(w2);
-    const float ur = wr * rinv, ui = wi * rinv;
-    const float a = c.srf * ur - c.sif * ui, b = c.srf * ui + c.sif * ur, aa = a * a;
-    const float atr = 0.5f * atanf(2.0f * a / (1.0f - float(c.epsabs)));
-    const float ati = 0.25f * kLn2f *
-                      (log2_f32((1.0f + b) * (1.0f + b) + aa) - log2_f32((1.0f - b) * (1.0f - b) + aa));
-    const float Sr = (atr * a + ati * b) * c.inv_epsabsf, Si = (ati * a - atr * b) * c.inv_epsabsf;
-    const float opr = 1.0f + Xr, opi = Xi, dd = rcp_f32(opr * opr + opi * opi);
-    const float nr = opr * dd - Sr, ni = -opi * dd - Si;
-    const float hx = 0.5f * rcp_f32(Xr * Xr + Xi * Xi);
-    m.SX = {(nr * Xr + ni * Xi) * hx, (ni * Xr - nr * Xi) * hx};
-    m.St = {0.f, 0.f};
-    const float A = c.bmassf * rinv;
-    m.A = A;
-    m.S = {Sr, Si};
-    m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};
-    return;
-  }
-  // the value series, dS/dt and, for small |eps|, dS/dy by synthetic division (ray_trace)
+  // A = B^t |w|^-t = 2^(t log2 B - (t/2) log2 |w|^2) (SIE: t = 1)
+  const float A = exp2_f32(fmaf(-0.5f * c.tf, l2w2, c.tlnb2));
+  const float ar = float(x - (c.g1 * x + c.g2 * y) - c.sxs) - sdx;
+  const float ai = float(y - (c.g2 * x - c.g1 * y) - c.sys) - sdy;
+  // series by synthetic division at y = -X (ray_trace): dS/dt (EPL) and, for small |eps|,
+  // dS/dy
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
   const bool sx_series = c.epsabs < kSxClosedMin;
   const int nd4 = (c.nterms_d + 3) & ~3;
-  float b1 = 0.f, b2 = 0.f, d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
+  float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
   if (sx_series) {
     for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
         const int n = n0 + q;
-        const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
-        b2 = b1;
-        b1 = b0;
         const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
         d2 = d1;
         d1 = d0;
-        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
-        t2 = t1;
-        t1 = t0;
+        if (MASS == 1) {
+          const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+          t2 = t1;
+          t1 = t0;
+        }
       }
     }
-  } else {
+  } else if (MASS == 1) {
     for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
-        const int n = n0 + q;
-        const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
-        b2 = b1;
-        b1 = b0;
-        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n0 + q]));
         t2 = t1;
         t1 = t0;
       }
     }
   }
-  const float Sr = fmaf(-yr, b2, b1), Si = yi * b2;
+  float Sr, Si;
+  if (!m.floored) {
+    // S = alpha conj(w) / (A |w|^2)
+    const float r = rcp_f32(A * w2);
+    Sr = (ar * wr + ai * wi) * r;
+    Si = (ai * wr - ar * wi) * r;
+  } else {
+    float b1 = 0.f, b2 = 0.f;
+    for (int n = nd4 - 1; n >= 0; --n) {
+      const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
+      b2 = b1;
+      b1 = b0;
+    }
+    Sr = fmaf(-yr, b2, b1);
+    Si = yi * b2;
+  }
   float dr, di;  // dS/dy
   if (sx_series) {
     dr = fmaf(-yr, d2, d1);
@@ -475,8 +475,9 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   } else {
     // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
     //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S
-    // (as series: the coefficient of (-X)^n on both sides agrees for every n). The numerator
-    // cancels like |X| = |eps|, so this is used for |eps| >= kSxClosedMin only.
+    // (as series: the coefficient of (-X)^n on both sides agrees for every n; for the SIE,
+    // t = 1, it is S_X = (1/(1+X) - S) / (2X), which the closed form atan(zeta)/zeta obeys).
+    // The numerator cancels like |X| = |eps|, so this is used for |eps| >= kSxClosedMin only.
     const float xsr = Xr * Sr - Xi * Si, xsi = Xr * Si + Xi * Sr;
     const float numr = c.hp * (1.0f - Sr) + c.hm * xsr;
     const float numi = -c.hp * Si + c.hm * xsi;
@@ -486,12 +487,10 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
     di = -(numi * denr - numr * deni) * inv;
   }
   m.SX = {-dr, -di};  // d/dX = -d/dy
-  m.St = {fmaf(-yr, t2, t1), yi * t2};
-  // A = B^t |w|^-t = 2^(t log2 B - (t/2) log2 |w|^2)
-  const float A = exp2_f32(fmaf(-0.5f * c.tf, l2w2, c.tlnb2));
+  m.St = MASS == 1 ? Cx{fmaf(-yr, t2, t1), yi * t2} : Cx{0.f, 0.f};
   m.A = A;
   m.S = {Sr, Si};
-  m.alpha = {A * (wr * Sr - wi * Si), A * (wr * Si + wi * Sr)};
+  m.alpha = {ar, ai};
 }
 
 // Adds the mass-parameter terms of g . d(beta)/d(theta) to acc, with g = d s / d beta
@@ -551,7 +550,7 @@ GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
   return L.i0 * exp2_f32(fmaf(-L.bnl, rho, L.bnl));
 }
 
-// Intensity plus the accumulator terms (weight sb) and d I / d(dx, dy).
+// Intensity plus the accumulator terms (weight sb) and the weighted sb dI/d(dx, dy).
 GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc, float& gdx,
                        float& gdy) {
   float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
@@ -563,9 +562,9 @@ GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc
   const float E = exp2_f32(fmaf(-L.bnl, rho, L.bnl));
   const float I = L.i0 * E;
   const float IQ = fl ? 0.0f : -I * L.bn * rho * L.inv2n * rcp_f32(q);
-  gdx = IQ * (2.0f * L.qa * dx + L.qb * dy);
-  gdy = IQ * (L.qb * dx + 2.0f * L.qc * dy);
   const float sI = sb * I, sIQ = sb * IQ, r2q = dx * dx + dy * dy + q;
+  gdx = sIQ * (2.0f * L.qa * dx + L.qb * dy);
+  gdy = sIQ * (L.qb * dx + 2.0f * L.qc * dy);
   acc[L_E] += sb * E;
   acc[L_RHO] += sI * rho;
   acc[L_RHO1] += sI * (rho - 1.0f);
@@ -580,10 +579,11 @@ GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc
 // g_n' = n g_(n-1). The Hermite functions are phi_n = (2^n n! sqrt(pi))^(-1/2) H_n e^(-u^2/2)
 // = pi^(-1/4) r_n g_n e^(-u^2/2) with r_n = sqrt(2^n / n!); the coefficients carry r_n1 r_n2
 // (hermite_scale) so that the sums run over the g_n directly.
+// Started from h0 instead of 1 the recurrence gives h0 g_n(u) (it is linear).
 template <int NMAX>
-GL_HD void hermite(float u, float* h) {
-  h[0] = 1.0f;
-  if (NMAX >= 1) h[1] = u;
+GL_HD void hermite(float u, float* h, float h0 = 1.0f) {
+  h[0] = h0;
+  if (NMAX >= 1) h[1] = h0 * u;
 #pragma unroll
   for (int n = 1; n < NMAX; ++n) h[n + 1] = fmaf(u, h[n], -(0.5f * n) * h[n - 1]);
 }
@@ -616,51 +616,47 @@ GL_HD float shapelet_fwd(const PConst& c, float sdx, float sdy, const float* shp
   return exp2_f32(-0.5f * kLog2e * (u * u + v * v)) * U;
 }
 
-// Shapelet intensity, accumulator terms (weight sb) and d I / d(beta_x, beta_y), using
+// Shapelet accumulator terms and the weighted derivatives sb dI/d(beta_x, beta_y), using
 // g_n' = n g_(n-1) for the scaled Hermite polynomials:
 //   dI/du = G (sum_n1 n1 g_(n1-1)(u) T_n1 - u U),
 //   dI/dv = G (sum_n1 g_n1(u) Tv_n1 - v U),  Tv_n1 = sum_n2 c'_(n1,n2) n2 g_(n2-1)(v),
 //   dI/dc_k = G g_n1(u) g_n2(v) r_n1 r_n2 / (beta sqrt(pi)) (the factor r_n1 r_n2 /
 //   (beta sqrt(pi)) is applied when the accumulators are mapped onto the gradient).
+// The u-polynomials are taken times sg = sb G, so every sum over them carries the weight:
+// U, Uu and Uv below are sb G times the sums above, and sb I = U.
 template <int NMAX>
-GL_HD float shapelet_adj(const PConst& c, float sdx, float sdy, float sb, float* acc, float& gbx,
-                         float& gby) {
+GL_HD void shapelet_adj(const PConst& c, float sdx, float sdy, const float* shp, float sb,
+                        float* acc, float& gbx, float& gby) {
   const float ib = c.inv_beta;
   const float u = sdx * ib, v = sdy * ib;
+  const float sg = sb * exp2_f32(-0.5f * kLog2e * (u * u + v * v));
   float hu[NMAX + 1], hv[NMAX + 1];
-  hermite<NMAX>(u, hu);
+  hermite<NMAX>(u, hu, sg);
   hermite<NMAX>(v, hv);
-  const float G = exp2_f32(-0.5f * kLog2e * (u * u + v * v));
-  const float sg = sb * G;
-  // g_0 = 1: sums start from their first term (see shapelet_fwd)
   float U = 0.f, Uu = 0.f, Uv = 0.f;
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1) {
-    float T = c.shp[shp_index(n1, 0)], Tv = 0.f;
+    // g_0(v) = 1: T starts from its n2 = 0 term (no addition of a zero)
+    float T = shp[shp_index(n1, 0)], Tv = 0.f;
 #pragma unroll
     for (int n2 = 1; n2 <= NMAX - n1; ++n2) {
-      const float ck = c.shp[shp_index(n1, n2)];
+      const float ck = shp[shp_index(n1, n2)];
       T = fmaf(ck, hv[n2], T);
       Tv = n2 == 1 ? ck : fmaf(ck, float(n2) * hv[n2 - 1], Tv);
     }
-    U = n1 == 0 ? T : fmaf(hu[n1], T, U);
-    if (n1 < NMAX) Uv = n1 == 0 ? Tv : fmaf(hu[n1], Tv, Uv);
-    if (n1 > 0) Uu = n1 == 1 ? T : fmaf(float(n1) * hu[n1 - 1], T, Uu);
+    U = n1 == 0 ? hu[0] * T : fmaf(hu[n1], T, U);
+    if (n1 < NMAX) Uv = n1 == 0 ? hu[0] * Tv : fmaf(hu[n1], Tv, Uv);
+    if (n1 > 0) Uu = n1 == 1 ? hu[0] * T : fmaf(float(n1) * hu[n1 - 1], T, Uu);
   }
-  float hvs[NMAX + 1];
-#pragma unroll
-  for (int n2 = 0; n2 <= NMAX; ++n2) hvs[n2] = sg * hv[n2];
 #pragma unroll
   for (int n1 = 0; n1 <= NMAX; ++n1)
 #pragma unroll
     for (int n2 = 0; n2 <= NMAX - n1; ++n2)
-      acc[A_SHP_C + shp_index(n1, n2)] = fmaf(hu[n1], hvs[n2], acc[A_SHP_C + shp_index(n1, n2)]);
-  const float I = G * U;
-  const float Iu = G * (Uu - u * U), Iv = G * (Uv - v * U);
-  acc[A_SHP_BETA] += sb * (-I - u * Iu - v * Iv) * ib;
+      acc[A_SHP_C + shp_index(n1, n2)] = fmaf(hu[n1], hv[n2], acc[A_SHP_C + shp_index(n1, n2)]);
+  const float Iu = Uu - u * U, Iv = Uv - v * U;  // sb dI/du, sb dI/dv
+  acc[A_SHP_BETA] += (-U - u * Iu - v * Iv) * ib;
   gbx = Iu * ib;
   gby = Iv * ib;
-  return I;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -786,6 +786,15 @@ subpix_adj_kernel(Group g) {
   float acc[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) acc[q] = 0.f;
+  // shapelet coefficients in vector registers (as in the forward pass): their sums then start
+  // from a register operand instead of a copy of a scalar one
+  constexpr int M = NMAX < 0 ? 1 : (NMAX + 1) * (NMAX + 2) / 2;
+  float shp[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    shp[q] = NMAX < 0 ? 0.f : c.shp[q];
+    asm("" : "+v"(shp[q]));
+  }
   for (int pix = p0 + threadIdx.x; pix < p1; pix += blockDim.x) {
     const int i = pix / W, j = pix - i * W;
     const float sb = sbar[pix];
@@ -795,28 +804,26 @@ subpix_adj_kernel(Group g) {
         const double x = s.x0 + double(j * k + b) * s.dxs;
         MassState m;
         const float* bp = reinterpret_cast<const float*>(beta + (a * k + b) * HW + pix);
-        const float2 sd =
-            make_float2(__builtin_nontemporal_load(bp), __builtin_nontemporal_load(bp + 1));
-        mass_jacobian_f32<MASS>(c, s_cf, s_nc, s_dc, x, y, m);
-        m.sdx = sd.x;
-        m.sdy = sd.y;
+        mass_jacobian_f32<MASS>(c, s_cf, s_nc, s_dc, x, y, __builtin_nontemporal_load(bp),
+                                __builtin_nontemporal_load(bp + 1), m);
+        // gx, gy: sb d(source light)/d(beta)
         float gx, gy;
         sersic_adj(c.src, m.sdx, m.sdy, sb, acc + A_SRC, gx, gy);
         if (NMAX >= 0) {
           float hx, hy;
-          shapelet_adj<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy, sb, acc, hx, hy);
+          shapelet_adj<(NMAX < 0 ? 0 : NMAX)>(c, m.sdx, m.sdy, shp, sb, acc, hx, hy);
           gx += hx;
           gy += hy;
         }
-        acc[A_SRC + L_DX] += sb * gx;
-        acc[A_SRC + L_DY] += sb * gy;
+        acc[A_SRC + L_DX] += gx;
+        acc[A_SRC + L_DY] += gy;
         if (LL) {
           float lx, ly;
           sersic_adj(c.lens, float(x - c.lxs), float(y - c.lys), sb, acc + A_LENS, lx, ly);
-          acc[A_LENS + L_DX] += sb * lx;
-          acc[A_LENS + L_DY] += sb * ly;
+          acc[A_LENS + L_DX] += lx;
+          acc[A_LENS + L_DY] += ly;
         }
-        mass_adjoint<MASS>(c, m, float(x), float(y), Cx{sb * gx, sb * gy}, acc);
+        mass_adjoint<MASS>(c, m, float(x), float(y), Cx{gx, gy}, acc);
       }
     }
   }
