@@ -85,6 +85,8 @@ GL_HD void decode_light(const float* th, LightC& L) {
   L.qa = float((1.0 + ee - 2.0 * e1) * den);
   L.qb = float(-4.0 * e2 * den);
   L.qc = float((1.0 + ee + 2.0 * e1) * den);
+  L.qbh = float(-2.0 * e2 * den);
+  L.kq = float(-(1.9992 * n - 0.3271) / n);
   L.inv2n = float(0.5 / n);
   L.l2re_n = float(log2(re) / n);
   L.bn = float(1.9992 * n - 0.3271);
@@ -493,11 +495,25 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   m.alpha = {ar, ai};
 }
 
-// Adds the mass-parameter terms of g . d(beta)/d(theta) to acc, with g = d s / d beta
-// (already weighted by the pixel adjoint). beta = x - alpha - alpha_ext.
+// Adds the mass-parameter terms g . d alpha/d(theta) to acc, with g = d s / d beta (already
+// weighted by the pixel adjoint); beta = x - alpha - alpha_ext, so the signs are applied at
+// the mapping. For a complex derivative D, g . D = Re(gb D) with gb = conj(g), and every
+// derivative is contracted with gb as soon as it is formed:
+//   with aw = d alpha/dw = A P1 and awb = d alpha/d conj(w) = A u2 P2 (eps fixed),
+//   U = gb aw, V = gb awb;
+//   d alpha/dz = aw - conj(eps) awb, d alpha/d conj(z) = awb - eps aw, and with x = z +
+//   conj z, y = i (z - conj z):
+//     g . d alpha/dx = Re((1 - eps) U + (1 - conj eps) V) = (1 - e1) Sp + e2 Dm,
+//     g . d alpha/dy = -Im((1 + eps) U - (1 + conj eps) V) = -(1 + e1) Dm - e2 Sp,
+//   Sp = Re U + Re V, Dm = Im U - Im V;
+//   d alpha/d eps = -tfac conj(eps) alpha - conj(z) aw,
+//   d alpha/d conj(eps) = -tfac eps alpha - z awb + A w u2 S_X (A depends on |eps|^2, X on
+//   conj(eps)); with eps = e1 + i e2 and W = gb A w u2 S_X:
+//     g . d alpha/de1 = -2 tfac e1 Re(gb alpha) - Re(z) Sp - Im(z) Dm + Re W,
+//     g . d alpha/de2 = -2 tfac e2 Re(gb alpha) + Re(z) Dm - Im(z) Sp + Im W;
+//   d alpha/dt = alpha (ln B - ln|w|^2 / 2) + A w S_t.
 template <int MASS>
 GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, Cx g, float* acc) {
-  // Wirtinger derivatives of alpha w.r.t. w and conj(w) (eps fixed)
   const Cx XSX = cmul(m.X, m.SX);
   Cx P1 = cadd(cscale(m.S, c.hp), XSX);  // (1 - t/2) S + X S_X
   Cx P2 = csub(cscale(m.S, c.hm), XSX);  // -(t/2) S - X S_X
@@ -505,32 +521,24 @@ GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, C
     P1 = cadd(m.S, cscale(XSX, 2.0f));
     P2 = {0.f, 0.f};
   }
-  const Cx aw = cscale(P1, m.A);
-  const Cx awb = cscale(cmul(m.u2, P2), m.A);
-  const Cx eps = {c.e1f, c.e2f}, epsb = {c.e1f, -c.e2f};
-  // d alpha / d z = aw - conj(eps) awb ; d alpha / d conj(z) = awb - eps aw
-  const Cx az = csub(aw, cmul(epsb, awb));
-  const Cx azb = csub(awb, cmul(eps, aw));
-  const Cx ax = cadd(az, azb);            // d alpha / d x
-  const Cx ay = cmuli(csub(az, azb));     // d alpha / d y
-  // d alpha / d eps and d alpha / d conj(eps)
-  const Cx zb = cconj(m.z);
-  const Cx ae = csub(cscale(cmul(m.alpha, epsb), -c.tfac), cmul(aw, zb));
-  Cx aeb = csub(cscale(cmul(m.alpha, eps), -c.tfac), cmul(awb, m.z));
-  aeb = cadd(aeb, cscale(cmul(cmul(m.w, m.u2), m.SX), m.A));
-  const Cx ae1 = cadd(ae, aeb);
-  const Cx ae2 = cmuli(csub(ae, aeb));
-  acc[A_M_ALPHA] += cdot(g, m.alpha);
+  const Cx gA = {g.r * m.A, -g.i * m.A};  // A gb
+  const Cx U = cmul(gA, P1);
+  const Cx V = cmul(gA, cmul(m.u2, P2));
+  const float Sp = U.r + V.r, Dm = U.i - V.i;
+  const float e1 = c.e1f, e2 = c.e2f;
+  const float ga = cdot(g, m.alpha);  // Re(gb alpha)
+  const Cx gAw = cmul(gA, m.w);
+  const Cx W = cmul(gAw, cmul(m.u2, m.SX));
+  acc[A_M_ALPHA] += ga;
   if (MASS == 1) {
-    // d alpha / d t = alpha (ln B - ln|w|^2 / 2) + A w S_t
-    Cx at = cscale(m.alpha, c.lnb - 0.5f * m.lnw2);
-    at = cadd(at, cscale(cmul(m.w, m.St), m.A));
-    acc[A_M_T] += cdot(g, at);
+    const float lt = fmaf(-0.5f, m.lnw2, c.lnb);  // ln B - ln|w|^2 / 2
+    acc[A_M_T] += fmaf(lt, ga, gAw.r * m.St.r - gAw.i * m.St.i);
   }
-  acc[A_M_E1] += cdot(g, ae1);
-  acc[A_M_E2] += cdot(g, ae2);
-  acc[A_M_X] += cdot(g, ax);
-  acc[A_M_Y] += cdot(g, ay);
+  const float k = -2.0f * c.tfac;
+  acc[A_M_E1] += fmaf(k * e1, ga, W.r - m.z.r * Sp - m.z.i * Dm);
+  acc[A_M_E2] += fmaf(k * e2, ga, W.i + m.z.r * Dm - m.z.i * Sp);
+  acc[A_M_X] += fmaf(1.0f - e1, Sp, e2 * Dm);
+  acc[A_M_Y] -= fmaf(1.0f + e1, Dm, e2 * Sp);
   acc[A_M_G1] += g.r * x - g.i * y;
   acc[A_M_G2] += g.r * y + g.i * x;
 }
@@ -550,28 +558,33 @@ GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
   return L.i0 * exp2_f32(fmaf(-L.bnl, rho, L.bnl));
 }
 
-// Intensity plus the accumulator terms (weight sb) and the weighted sb dI/d(dx, dy).
-GL_HD float sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc, float& gdx,
-                       float& gdy) {
-  float q = L.qa * dx * dx + L.qb * dx * dy + L.qc * dy * dy;
+// Accumulator terms (weight sb) and the weighted sb dI/d(dx, dy). With the half gradient of
+// R^2, (px, py) = (qa dx + qb dy / 2, qb dx / 2 + qc dy), R^2 = dx px + dy py and
+// dR^2/d(dx, dy) = 2 (px, py); dI/dR^2 = -I b_n rho / (2 n R^2), so
+// 2 sb dI/dR^2 = sb I rho (-b_n / n) / R^2 =: sIQ2 and sb dI/d(dx, dy) = sIQ2 (px, py).
+// Slots: L_E: sb E; L_RHO: sb I rho; L_RHO1: sb I (rho - 1); L_RHOLN: sb I rho log2(rho)
+// (ln 2 is applied at the mapping); L_Q1, L_Q2: the two eccentricity terms times
+// 2 sb dI/dR^2 (the 1/2 is applied at the mapping).
+GL_HD void sersic_adj(const LightC& L, float dx, float dy, float sb, float* acc, float& gdx,
+                      float& gdy) {
+  const float px = fmaf(L.qa, dx, L.qbh * dy), py = fmaf(L.qc, dy, L.qbh * dx);
+  float q = fmaf(dx, px, dy * py);
   const bool fl = q < kR2Floor;
   q = fl ? kR2Floor : q;
   const float l2rho = fmaf(log2_f32(q), L.inv2n, -L.l2re_n);
-  const float lnrho = kLn2f * l2rho;
   const float rho = exp2_f32(l2rho);
-  const float E = exp2_f32(fmaf(-L.bnl, rho, L.bnl));
-  const float I = L.i0 * E;
-  const float IQ = fl ? 0.0f : -I * L.bn * rho * L.inv2n * rcp_f32(q);
-  const float sI = sb * I, sIQ = sb * IQ, r2q = dx * dx + dy * dy + q;
-  gdx = sIQ * (2.0f * L.qa * dx + L.qb * dy);
-  gdy = sIQ * (L.qb * dx + 2.0f * L.qc * dy);
-  acc[L_E] += sb * E;
-  acc[L_RHO] += sI * rho;
-  acc[L_RHO1] += sI * (rho - 1.0f);
-  acc[L_RHOLN] += sI * rho * lnrho;
-  acc[L_Q1] += sIQ * (L.e1 * r2q - dx * dx + dy * dy);
-  acc[L_Q2] += sIQ * (L.e2 * r2q - 2.0f * dx * dy);
-  return I;
+  const float sE = sb * exp2_f32(fmaf(-L.bnl, rho, L.bnl));
+  const float sI = L.i0 * sE, sIr = sI * rho;
+  const float sIQ2 = fl ? 0.0f : sIr * L.kq * rcp_f32(q);
+  gdx = sIQ2 * px;
+  gdy = sIQ2 * py;
+  const float r2q = fmaf(dx, dx, fmaf(dy, dy, q));
+  acc[L_E] += sE;
+  acc[L_RHO] += sIr;
+  acc[L_RHO1] += sIr - sI;
+  acc[L_RHOLN] = fmaf(sIr, l2rho, acc[L_RHOLN]);
+  acc[L_Q1] = fmaf(sIQ2, fmaf(L.e1, r2q, fmaf(dy, dy, -dx * dx)), acc[L_Q1]);
+  acc[L_Q2] = fmaf(sIQ2, fmaf(L.e2, r2q, -2.0f * dx * dy), acc[L_Q2]);
 }
 
 // Scaled Hermite polynomials g_n(u) = H_n(u) / 2^n (H_n the physicists' polynomials):
@@ -664,8 +677,8 @@ GL_HD void shapelet_adj(const PConst& c, float sdx, float sdy, const float* shp,
 // ------------------------------------------------------------------------------------------
 GL_HD void light_grad(const LightC& L, const double* a, float* g) {
   g[0] = float(a[L_RHO] * L.bn / (double(L.n) * L.re));                 // R_eff
-  g[1] = float(-1.9992 * a[L_RHO1] + L.bn / double(L.n) * a[L_RHOLN]);  // n
-  const double ge1 = 2.0 * L.inv1me2 * a[L_Q1], ge2 = 2.0 * L.inv1me2 * a[L_Q2];
+  g[1] = float(-1.9992 * a[L_RHO1] + L.bn / double(L.n) * kLn2 * a[L_RHOLN]);  // n
+  const double ge1 = L.inv1me2 * a[L_Q1], ge2 = L.inv1me2 * a[L_Q2];
   g[2] = float(L.j11 * ge1 + L.j12 * ge2);                               // eps1
   g[3] = float(L.j12 * ge1 + L.j22 * ge2);                               // eps2
   g[4] = float(-a[L_DX]);                                                // x

@@ -40,6 +40,8 @@ static_assert(A_SHP_C + kMaxShp <= kNAcc, "accumulator slots");
 // Elliptical Sersic constants of one particle.
 struct LightC {
   float qa, qb, qc;    // R^2 = qa dx^2 + qb dx dy + qc dy^2
+  float qbh;           // qb / 2
+  float kq;            // -b_n / n
   float inv2n;         // 1 / (2n)
   float l2re_n;        // log2(R_eff) / n
   float bn, i0;        // b_n = 1.9992 n - 0.3271, I0
