@@ -142,7 +142,6 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   c.ycf = float(c.yc);
   c.w2floorf = float(c.w2floor);
   c.tlnb2 = float(c.tlnb * 1.4426950408889634);
-  c.bmassf = float(B);
   c.tfac = float(t / (2.0 * (1.0 - ee)));
   c.mj11 = float(j11);
   c.mj12 = float(j12);
@@ -167,9 +166,8 @@ GL_HD void decode_mass(const float* th, int mass, int shear, PConst& c) {
   } else {
     c.sr = c.si = 0.0;
   }
-  c.srf = float(c.sr);
-  c.sif = float(c.si);
-  c.inv_epsabsf = eabs > 0.0 ? float(1.0 / eabs) : 0.f;
+  c.iebr = eabs >= kSxClosedMin ? float(e1 / ee) : 0.f;
+  c.iebi = eabs >= kSxClosedMin ? float(e2 / ee) : 0.f;
 }
 
 // Series ratio c_n / c_{n-1} = (2n - 2 + t) / (2n + 2 - t) and the increment of
@@ -320,7 +318,7 @@ struct MassState {
   Cx z, w, u2, X;     // z, w, w^2/|w|^2, X = conj(eps) u2
   float lnw2;         // ln |w|^2 (floored)
   float A;            // B^t |w|^-t
-  Cx S, SX, St;       // S_t(X), dS/dX, dS/dt
+  Cx S, XSX, U2SX, St;  // S_t(X), X dS/dX, u2 dS/dX, dS/dt
   Cx alpha;
   int floored;        // |w|^2 hit the floor
 };
@@ -383,8 +381,8 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, d
   sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
 }
 
-// The lens quantities the adjoint needs, in FP32: z, w, u2, X, ln|w|^2, A, S, dS/dX, dS/dt,
-// alpha. (sdx, sdy) is beta - x_s of the forward pass's FP64 ray trace (SysDesc::beta): the
+// The lens quantities the adjoint needs, in FP32: z, w, u2, X, ln|w|^2, A, S, X dS/dX,
+// u2 dS/dX, dS/dt, alpha. (sdx, sdy) is beta - x_s of the forward pass's FP64 ray trace (SysDesc::beta): the
 // light profiles and their derivatives are evaluated there (an FP32 ray trace moves it by
 // ~3e-7 arcsec, which shows at 2e-3 in the gradient of a vector far from the posterior). The
 // rest only enters the Jacobian d(beta)/d(theta) and the local derivatives, whose tolerance
@@ -470,25 +468,25 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
     Sr = fmaf(-yr, b2, b1);
     Si = yi * b2;
   }
-  float dr, di;  // dS/dy
   if (sx_series) {
-    dr = fmaf(-yr, d2, d1);
-    di = yi * d2;
+    const Cx SX = {-fmaf(-yr, d2, d1), -yi * d2};  // dS/dX = -dS/dy
+    m.XSX = cmul(m.X, SX);
+    m.U2SX = cmul(m.u2, SX);
   } else {
     // S = sum c_n (-X)^n with c_n / c_(n-1) = (2n - 2 + t) / (2n + 2 - t) obeys
     //   X (1 + X) dS/dX = (1 - t/2)(1 - S) - (t/2) X S
     // (as series: the coefficient of (-X)^n on both sides agrees for every n; for the SIE,
-    // t = 1, it is S_X = (1/(1+X) - S) / (2X), which the closed form atan(zeta)/zeta obeys).
-    // The numerator cancels like |X| = |eps|, so this is used for |eps| >= kSxClosedMin only.
+    // t = 1, it is S_X = (1/(1+X) - S) / (2X), which the closed form atan(zeta)/zeta obeys),
+    // so X dS/dX is the right side over 1 + X, and u2 dS/dX = X dS/dX / conj(eps), as
+    // X = conj(eps) u2. The numerator cancels like |X| = |eps|, so this is used for
+    // |eps| >= kSxClosedMin only.
     const float xsr = Xr * Sr - Xi * Si, xsi = Xr * Si + Xi * Sr;
     const float numr = c.hp * (1.0f - Sr) + c.hm * xsr;
     const float numi = -c.hp * Si + c.hm * xsi;
-    const float denr = Xr + Xr * Xr - Xi * Xi, deni = Xi + 2.0f * Xr * Xi;
-    const float inv = rcp_f32(denr * denr + deni * deni);
-    dr = -(numr * denr + numi * deni) * inv;  // dS/dy = -dS/dX
-    di = -(numi * denr - numr * deni) * inv;
+    const float opr = 1.0f + Xr, inv = rcp_f32(opr * opr + Xi * Xi);
+    m.XSX = {(numr * opr + numi * Xi) * inv, (numi * opr - numr * Xi) * inv};
+    m.U2SX = cmul(m.XSX, Cx{c.iebr, c.iebi});
   }
-  m.SX = {-dr, -di};  // d/dX = -d/dy
   m.St = MASS == 1 ? Cx{fmaf(-yr, t2, t1), yi * t2} : Cx{0.f, 0.f};
   m.A = A;
   m.S = {Sr, Si};
@@ -514,7 +512,7 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
 //   d alpha/dt = alpha (ln B - ln|w|^2 / 2) + A w S_t.
 template <int MASS>
 GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, Cx g, float* acc) {
-  const Cx XSX = cmul(m.X, m.SX);
+  const Cx XSX = m.XSX;
   Cx P1 = cadd(cscale(m.S, c.hp), XSX);  // (1 - t/2) S + X S_X
   Cx P2 = csub(cscale(m.S, c.hm), XSX);  // -(t/2) S - X S_X
   if (m.floored) {  // |w|^2 frozen at the floor: X = conj(eps) w^2 / floor
@@ -528,7 +526,7 @@ GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, C
   const float e1 = c.e1f, e2 = c.e2f;
   const float ga = cdot(g, m.alpha);  // Re(gb alpha)
   const Cx gAw = cmul(gA, m.w);
-  const Cx W = cmul(gAw, cmul(m.u2, m.SX));
+  const Cx W = cmul(gAw, m.U2SX);
   acc[A_M_ALPHA] += ga;
   if (MASS == 1) {
     const float lt = fmaf(-0.5f, m.lnw2, c.lnb);  // ln B - ln|w|^2 / 2

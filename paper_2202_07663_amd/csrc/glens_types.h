@@ -78,7 +78,7 @@ struct PConst {
   float xcf, ycf;      // lens centre (FP32, adjoint Jacobian)
   float w2floorf;      // R^2 floor on |w|^2 (FP32)
   float tlnb2;         // t ln B log2(e)
-  float srf, sif, bmassf, inv_epsabsf;  // SIE closed form in FP32 (adjoint Jacobian)
+  float iebr, iebi;    // 1 / conj(eps) for |eps| >= kSxClosedMin, else 0 (adjoint Jacobian)
   float e1f, e2f;
   float lnb;
   float tfac;          // t / (2 (1 - |eps|^2))
