@@ -167,6 +167,32 @@ def test_mass_ellipticity_range(glens, eps, epl):
     assert_grad_close(g, g_ref, names=spec.names)
 
 
+@pytest.mark.parametrize("epl", [False, True])
+def test_lens_centre_on_a_sub_pixel(glens, epl):
+    """A lens centre exactly on a sub-pixel, where the elliptical radius sits at its floor on
+    both sides (the adjoint then sums the value series there instead of taking S from alpha).
+    The deflection there is zero, so log L and the light-parameter gradient are defined and
+    compared with the oracle; the mass-parameter gradient takes that sub-pixel's frozen-radius
+    derivative, which the two sides define on different radii, so it is only checked to be
+    finite."""
+    spec = synth.Spec("c", 31, 31, 1, epl=epl, lens_light=False, nmax=2,
+                      psf=synth.moffat_psf(7, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
+    truth = synth.draw_truth(spec, 12)
+    ic = 4 if epl else 3  # lens centre (x, y): pixel (15, 15) is centred on the origin
+    truth[ic] = truth[ic + 1] = 0.0
+    om = oracle_model(spec)
+    obs = synth.add_noise(oracle.simulate(om, truth.astype(np.float64))[0], 12, 0.1, 1000.0)
+    theta = synth.draw_particles(spec, truth, 8, seed=3)
+    theta[:, ic] = theta[:, ic + 1] = 0.0
+    m = glens.Model.from_spec(spec, obs)
+    ll, g = _run(m, theta)
+    ll_ref, g_ref = oracle.loglik_grad(om, theta.astype(np.float64), obs)
+    assert_logl_close(ll, ll_ref)
+    assert np.all(np.isfinite(g))
+    nm = ic + 2 + 2 * int(spec.shear)  # mass parameters come first
+    assert_grad_close(g[:, nm:], g_ref[:, nm:], names=spec.names[nm:])
+
+
 # ------------------------------------------------------------------------------------------
 # Edge cases and API behaviour
 # ------------------------------------------------------------------------------------------
