@@ -504,7 +504,11 @@ __device__ __forceinline__ void mfma_pass(MfmaPass& P, const uint16_t* x, int ne
 #undef GL_G
 }
 
-__global__ void __launch_bounds__(kConvThreads) conv_mfma_kernel(Group g) {
+// Four waves per SIMD (at most 128 VGPRs) and at most 40 KB of LDS at the 60 x 60, K = 21
+// size let four workgroups share a CU: 4096 particles then fill the chip in four rounds
+// instead of five and a third.
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(4)))
+conv_mfma_kernel(Group g) {
   extern __shared__ __align__(16) uint16_t xlds[];
   __shared__ double red[kConvThreads / 64];
   __shared__ float redf[kConvThreads / 64];
@@ -513,7 +517,7 @@ __global__ void __launch_bounds__(kConvThreads) conv_mfma_kernel(Group g) {
   const int part = blockIdx.x - g.block0[si];
   const int H = s.H, W = s.W, HW = H * W, K = s.K, C = (K - 1) / 2, mode = s.mode;
   const MfmaGeom q = mfma_geom(H, W, K);
-  const int nel = q.Hq * q.pitch;  // fp16 per part (a multiple of 8)
+  const int nel = q.Hq * q.pitch;  // fp16 per part (a multiple of 4)
   float* seed = reinterpret_cast<float*>(xlds + 2 * nel);
   for (int i = threadIdx.x; i < nel / 4; i += blockDim.x)
     reinterpret_cast<uint4*>(xlds)[i] = make_uint4(0u, 0u, 0u, 0u);

@@ -151,7 +151,7 @@ struct MfmaGeom {
   int N;       // useful output columns per tile
   int TR, TC;  // tile rows / columns
   int T;       // tiles
-  int Hq;      // rows of the padded image in LDS
+  int Hq;      // rows of the padded image in LDS (image and halo: H + K - 1)
   int pitch;   // row pitch in 16-bit elements (a multiple of 4)
 };
 __host__ __device__ inline MfmaGeom mfma_geom(int H, int W, int K) {
@@ -160,13 +160,17 @@ __host__ __device__ inline MfmaGeom mfma_geom(int H, int W, int K) {
   q.TR = (H + 15) / 16;
   q.TC = (W + q.N - 1) / q.N;
   q.T = q.TR * q.TC;
-  q.Hq = q.TR * 16 + K - 1;
+  q.Hq = H + K - 1;
   q.pitch = ((q.TC - 1) * q.N + 32 + 3) & ~3;  // the last tile's 32-column window
   return q;
 }
-// LDS bytes of the pass: the padded image as two fp16 parts, and the FP32 pixel seed.
+// LDS bytes of the pass: the padded image as two fp16 parts, and the FP32 pixel seed. The
+// tiles' last 16 - H % 16 rows (outputs past the image, never used) read up to 16 TR - H
+// rows past each part; past the second part those reads fall in the seed area, which is
+// made at least that long.
 __host__ __device__ inline int mfma_lds_bytes(const MfmaGeom& q, int H, int W) {
-  return 4 * q.Hq * q.pitch + 4 * H * W;
+  const int over = 2 * (q.TR * 16 - H) * q.pitch;
+  return 4 * q.Hq * q.pitch + (4 * H * W > over ? 4 * H * W : over);
 }
 
 constexpr int kMaxGroup = 10;
