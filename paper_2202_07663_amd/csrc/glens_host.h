@@ -87,6 +87,7 @@ constexpr size_t kConvLdsMax = 160 * 1024 - 256;  // dynamic LDS allowed to the 
 // Block counts of one system per stage.
 inline int blocks_prologue(const SysDesc& s) { return s.P; }  // prologue, finalize
 inline int blocks_subpix(const SysDesc& s) { return s.P * s.tiles; }
+inline int blocks_subpix_fwd(const SysDesc& s) { return s.P * s.ftiles; }
 inline int blocks_conv(const SysDesc& s) { return s.P; }
 inline int blocks_conv_band(const SysDesc& s) { return s.P * s.bands; }
 // Row bands of the PSF pass for P particles of an H-row image (1: the whole-image kernel).

@@ -139,14 +139,14 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int si = find_sys(g, blockIdx.x);
   const SysDesc& s = g.sys[si];
   const int lb = blockIdx.x - g.block0[si];
-  const int part = lb / s.tiles, tile = lb - part * s.tiles;
+  const int part = lb / s.ftiles, tile = lb - part * s.ftiles;
   const PConst& c = s.pc[part];
   __shared__ double s_c[kMaxTerms];
   __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
   stage_series(c, s_c, s_nc, s_dc);
   const int HW = s.H * s.W;
-  const int p0 = tile * s.pix_per_tile;
-  const int p1 = min(HW, p0 + s.pix_per_tile);
+  const int p0 = tile * s.fpix_per_tile;
+  const int p1 = min(HW, p0 + s.fpix_per_tile);
   float2* beta = s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW : nullptr;
   forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, beta, p0, p1);
 }

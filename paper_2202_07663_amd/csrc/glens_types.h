@@ -106,8 +106,10 @@ struct SysDesc {
   float s2b, inv_gt;   // sigma_bkg^2, 1 / (G t_exp)
   int mass, shear, lens_light, nmax, d;
   int P;
-  int tiles;           // sub-pixel work tiles per particle
+  int tiles;           // sub-pixel work tiles per particle (adjoint; its accumulator rows)
   int pix_per_tile;
+  int ftiles;          // the same for the forward pass
+  int fpix_per_tile;
   int mode;            // conv kernel: 0 image, 1 log L, 2 log L + adjoint seed
   int bands;           // banded PSF pass: row bands per particle (1: whole image)
   int band_rows;       // rows per band (a multiple of the strip height)
