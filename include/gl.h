@@ -14,7 +14,9 @@
  *     current HIP device; they are never freed or retained by the library. Host buffers
  *     named in descriptors (psf, obs, priors) are copied before the call returns.
  *   - Compute calls are stream-ordered: `stream` is a hipStream_t (NULL = default stream).
- *     They enqueue work and return; outputs are valid once the stream is synchronised.
+ *     They enqueue work and return; outputs are valid once the stream is synchronised. The
+ *     one exception: a call on a batch larger than the model's work space grows it first,
+ *     which synchronises the device (gl_model_reserve sizes it up front).
  *     Calls on one gl_model must be ordered on one stream (the model owns the work space).
  *   - Parameter vectors theta are FP32, row-major [P][d], physical (constrained) values in
  *     this order (Sec. 2.1.2, eq. sim-dist; arcsec for lengths, counts/s for intensities):
@@ -65,7 +67,7 @@ enum { GL_MASS_SIE = 0, GL_MASS_EPL = 1 };
  */
 typedef struct gl_model_desc {
   int H, W;            /* image rows and columns, 1..GL_MAX_IMAGE */
-  float pixel_scale;   /* arcsec per pixel, > 0 */
+  float pixel_scale;   /* arcsec per pixel; pixel_scale / k_super >= 1e-4 */
   int k_super;         /* supersampling factor, 1..GL_MAX_KSUPER */
   int mass;            /* GL_MASS_SIE or GL_MASS_EPL */
   int shear;           /* 1: external shear (2 parameters), 0: none */
@@ -93,6 +95,29 @@ int gl_model_destroy(gl_model* model);
 
 /* Number d of parameters per vector for this model (layout above). */
 int gl_model_nparams(const gl_model* model, int* d);
+
+/* Grow the model's device work space for calls of up to P parameter vectors (any batch size
+ * up to P). The compute calls grow it on demand, and a call that grows it synchronises the
+ * device and reallocates before it enqueues its work; reserving first keeps later calls
+ * enqueue-only. with_fit = 1 also reserves the buffers of gl_fit_state_*, gl_vi_* and
+ * gl_hmc_* (they are kept once present). GL_E_NOMEM if the device memory is not there. */
+int gl_model_reserve(gl_model* model, int P, int with_fit);
+
+/* Diagnostic: how a call with P parameter vectors is split on this model (no device work).
+ *   psf_path:  GL_PSF_MFMA (matrix cores, one workgroup per vector: P >= 512, K <= 21, the
+ *              image in at most 64 tiles of 16 rows), GL_PSF_VALU (vector ALUs, one
+ *              workgroup per vector) or GL_PSF_BANDED (vector ALUs, row bands of the image
+ *              per vector, for P < 512);
+ *   tiles, fwd_tiles: sub-pixel work tiles per vector of the adjoint and the forward pass;
+ *   bands:     row bands of the PSF pass (1 unless banded);
+ *   workspace_bytes: device work space of a likelihood call at this P (gl_model_reserve);
+ *   workspace_reserved: what the model holds now. */
+enum { GL_PSF_MFMA = 0, GL_PSF_VALU = 1, GL_PSF_BANDED = 2 };
+typedef struct gl_plan {
+  int psf_path, tiles, fwd_tiles, bands;
+  size_t workspace_bytes, workspace_reserved;
+} gl_plan;
+int gl_model_plan(const gl_model* model, int P, gl_plan* out);
 
 /* Noiseless model image I_model(x, y; Theta) (Sec. 2.1.1: deflect, ray trace, source plus
  * lens light, k x k mean, PSF) for P parameter vectors.
@@ -343,10 +368,15 @@ int gl_submit(gl_server* s, const gl_model_desc* desc, const gl_fit_opts* opts,
  * (the ticket is then released); GL_E_NOTFOUND for an unknown ticket. */
 int gl_poll(gl_server* s, uint64_t ticket, gl_fit_result* out);
 
+/* Counters of the server. completed counts every retired request, failed those retired with
+ * an error status (admission that could not allocate, a launch that failed, a device error:
+ * gl_poll then returns the result with that status), last_error the code of the latest. */
 typedef struct gl_server_stats {
   uint64_t submitted, admitted, completed, ticks;
   size_t hbm_in_use, hbm_peak;
   int active, queued;
+  uint64_t failed;
+  int last_error;
 } gl_server_stats;
 int gl_server_get_stats(gl_server* s, gl_server_stats* out);
 

@@ -43,6 +43,8 @@ def lib():
         _lib = ctypes.CDLL(_LIB_PATH)
         _lib.or_nparams.restype = ctypes.c_int
         _lib.or_num_threads.restype = ctypes.c_int
+        _lib.or_set_num_threads.argtypes = [ctypes.c_int]
+        _lib.or_set_num_threads.restype = None
         _lib.or_loglik_grad.restype = ctypes.c_int
         _lib.or_log_likelihood_image.restype = ctypes.c_double
     return _lib
@@ -89,6 +91,11 @@ class Model:
 def num_threads() -> int:
     """Threads the oracle's parallel loops use (OpenMP)."""
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later parallel loops (the CPU baseline times 1 and all)."""
+    lib().or_set_num_threads(int(n))
 
 
 def simulate(m: Model, theta) -> np.ndarray:

@@ -477,6 +477,14 @@ static Model to_model(const or_model_desc* d) {
 int or_nparams(const or_model_desc* d) { return n_params(to_model(d)); }
 
 // Threads the parallel loops below use.
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

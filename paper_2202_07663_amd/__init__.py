@@ -115,6 +115,21 @@ class Model:
             raise ValueError(f"theta must be float32 [P, {self.d}]")
         return theta.contiguous()
 
+    PSF_PATHS = {_lib.GL_PSF_MFMA: "mfma", _lib.GL_PSF_VALU: "valu", _lib.GL_PSF_BANDED: "banded"}
+
+    def reserve(self, P: int, with_fit: bool = False):
+        """Size the device work space for calls of up to P vectors (later calls then only
+        enqueue work)."""
+        check(lib().gl_model_reserve(self._h, int(P), int(with_fit)))
+
+    def plan(self, P: int) -> dict:
+        """How a call with P vectors is split: PSF path, tiles, bands, work-space bytes."""
+        r = _lib.Plan()
+        check(lib().gl_model_plan(self._h, int(P), ctypes.byref(r)))
+        return {"psf_path": self.PSF_PATHS[r.psf_path], "tiles": r.tiles,
+                "fwd_tiles": r.fwd_tiles, "bands": r.bands,
+                "workspace_bytes": r.workspace_bytes, "workspace_reserved": r.workspace_reserved}
+
     def simulate(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
         theta = self._theta(theta)
         P = theta.shape[0]

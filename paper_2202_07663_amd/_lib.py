@@ -85,7 +85,17 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
                 ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
-                ("active", ctypes.c_int), ("queued", ctypes.c_int)]
+                ("active", ctypes.c_int), ("queued", ctypes.c_int),
+                ("failed", ctypes.c_uint64), ("last_error", ctypes.c_int)]
+
+
+GL_PSF_MFMA, GL_PSF_VALU, GL_PSF_BANDED = 0, 1, 2
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("psf_path", ctypes.c_int), ("tiles", ctypes.c_int), ("fwd_tiles", ctypes.c_int),
+                ("bands", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
+                ("workspace_reserved", ctypes.c_size_t)]
 
 
 _vp = ctypes.c_void_p
@@ -94,6 +104,8 @@ _SIGNATURES = {
     "gl_model_create": [ctypes.POINTER(ModelDesc), ctypes.POINTER(_vp)],
     "gl_model_destroy": [_vp],
     "gl_model_nparams": [_vp, ctypes.POINTER(_i)],
+    "gl_model_reserve": [_vp, _i, _i],
+    "gl_model_plan": [_vp, _i, ctypes.POINTER(Plan)],
     "gl_simulate": [_vp, _vp, _i, _vp, _vp],
     "gl_loglik": [_vp, _vp, _i, _vp, _vp],
     "gl_loglik_grad": [_vp, _vp, _i, _vp, _vp, _vp],

@@ -28,13 +28,6 @@ int set_error(int code, const char* fmt, ...) {
 }
 void clear_error() { t_err.clear(); }
 
-#define GL_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
-                       #call, hipGetErrorString(e_));                                    \
-  } while (0)
 
 int check_device_ptr(const void* p, const char* name) {
   if (!p) return set_error(GL_E_INVALID, "%s is NULL", name);
@@ -67,6 +60,9 @@ int validate_desc(const gl_model_desc* d, ModelCfg* c) {
   if (d->k_super < 1) return set_error(GL_E_INVALID, "k_super must be >= 1");
   if (d->k_super > GL_MAX_KSUPER)
     return set_error(GL_E_UNIMPLEMENTED, "k_super above %d", GL_MAX_KSUPER);
+  if (double(d->pixel_scale) / d->k_super < kMinPitch)
+    return set_error(GL_E_UNIMPLEMENTED, "sub-pixel pitch pixel_scale / k_super below %g arcsec",
+                     kMinPitch);
   if (d->mass != GL_MASS_SIE && d->mass != GL_MASS_EPL)
     return set_error(GL_E_INVALID, "mass must be GL_MASS_SIE or GL_MASS_EPL");
   if (d->shear != 0 && d->shear != 1) return set_error(GL_E_INVALID, "shear must be 0 or 1");
@@ -192,32 +188,27 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 int beta_per_particle(const ModelCfg& c) { return c.k * c.k * c.H * c.W; }
 
-size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit, int beta_pp) {
+// Accumulator rows (particle x tile) that calls of up to P vectors need: the tile count
+// grows as P shrinks (choose_tiles), so the largest P tiles is taken over every batch size
+// up to P (above 2048 particles there is one tile each).
+size_t acc_rows_upto(int P, int HW) {
+  size_t rows = 0;
+  for (int p = std::max(1, std::min(P, 2049)); p >= 1; --p)
+    rows = std::max(rows, size_t(p) * choose_tiles(p, HW));
+  return std::max(rows, size_t(std::max(P, 0)) * choose_tiles(std::max(P, 1), HW));
+}
+
+size_t workspace_bytes(int P, size_t rows, int HW, int d, bool fit, int beta_pp) {
   size_t b = align256(sizeof(PConst) * P) + 3 * align256(sizeof(float) * (size_t)P * HW) +
-             align256(sizeof(double) * (size_t)P * tiles * kNAcc) +
+             align256(sizeof(double) * rows * kNAcc) +
              align256(sizeof(double) * (size_t)P * kConvMaxBands * 2) +
              align256(sizeof(float2) * (size_t)P * beta_pp);
   if (fit) b += align256(sizeof(double) * P) + 2 * align256(sizeof(float) * (size_t)P * d);
   return b;
 }
 
-void workspace_free(Workspace& ws) {
-  if (ws.pc) (void)hipFree(ws.pc);
-  ws = Workspace();
-}
-
-int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit, int beta_pp) {
-  if (ws.pc && P <= ws.cap_P && tiles <= ws.cap_tiles && HW == ws.HW && beta_pp == ws.beta_pp &&
-      (!fit || ws.logl))
-    return GL_OK;
-  const int cP = std::max(P, ws.cap_P), cT = std::max(tiles, ws.cap_tiles);
-  if (ws.pc) {
-    GL_HIP(hipDeviceSynchronize());
-    workspace_free(ws);
-  }
-  const size_t bytes = workspace_bytes(cP, cT, HW, d, fit, beta_pp);
-  char* base = nullptr;
-  GL_HIP(hipMalloc(&base, bytes));
+void workspace_layout(Workspace& ws, char* base, int cP, size_t rows, int HW, int d, bool fit,
+                      int beta_pp) {
   size_t off = 0;
   auto take = [&](size_t b) {
     char* p = base + off;
@@ -227,21 +218,51 @@ int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit, 
   ws.pc = reinterpret_cast<PConst*>(take(sizeof(PConst) * cP));
   ws.m0 = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
   ws.sbar = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
-  ws.acc = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * cT * kNAcc));
+  ws.acc = reinterpret_cast<double*>(take(sizeof(double) * rows * kNAcc));
   ws.seed = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * HW));
   ws.lpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cP * kConvMaxBands * 2));
   ws.beta = beta_pp ? reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)cP * beta_pp))
                     : nullptr;
   ws.beta_pp = beta_pp;
+  ws.logl = nullptr;
+  ws.grad = ws.theta = nullptr;
   if (fit) {
     ws.logl = reinterpret_cast<double*>(take(sizeof(double) * cP));
     ws.grad = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
     ws.theta = reinterpret_cast<float*>(take(sizeof(float) * (size_t)cP * d));
   }
   ws.cap_P = cP;
-  ws.cap_tiles = cT;
+  ws.cap_rows = rows;
   ws.HW = HW;
-  ws.bytes = bytes;
+  ws.bytes = off;
+}
+
+void workspace_free(Workspace& ws) {
+  if (ws.pc) (void)hipFree(ws.pc);
+  ws = Workspace();
+}
+
+int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit, int beta_pp) {
+  // a regrow keeps the fit buffers an earlier fit, VI or HMC call asked for: their users
+  // rebuild their launch descriptors from ws after reserving, but a later plain likelihood
+  // call on a larger batch must not drop them
+  fit = fit || ws.logl != nullptr;
+  const size_t rows = size_t(P) * tiles;
+  if (ws.pc && P <= ws.cap_P && rows <= ws.cap_rows && HW == ws.HW && beta_pp == ws.beta_pp &&
+      (!fit || ws.logl))
+    return GL_OK;
+  // grow to at least every batch size up to P, so that a smaller batch (more tiles per
+  // particle) does not regrow it again
+  const int cP = std::max(P, ws.cap_P);
+  const size_t cR = std::max({rows, ws.cap_rows, acc_rows_upto(cP, HW)});
+  if (ws.pc) {
+    GL_HIP(hipDeviceSynchronize());
+    workspace_free(ws);
+  }
+  const size_t bytes = workspace_bytes(cP, cR, HW, d, fit, beta_pp);
+  char* base = nullptr;
+  GL_HIP(hipMalloc(&base, bytes));
+  workspace_layout(ws, base, cP, cR, HW, d, fit, beta_pp);
   return GL_OK;
 }
 
@@ -558,6 +579,36 @@ int gl_model_nparams(const gl_model* m, int* d) {
   clear_error();
   if (!m || !d) return set_error(GL_E_INVALID, "NULL argument");
   *d = m->sys.cfg.d;
+  return GL_OK;
+}
+
+int gl_model_reserve(gl_model* m, int P, int with_fit) {
+  clear_error();
+  if (!m) return set_error(GL_E_INVALID, "model is NULL");
+  if (P < 0) return set_error(GL_E_INVALID, "P must be >= 0");
+  if (P == 0) return GL_OK;
+  const ModelCfg& c = m->sys.cfg;
+  const int HW = c.H * c.W;
+  // every batch size up to P: workspace_reserve grows to acc_rows_upto(P) rows
+  return workspace_reserve(m->ws, P, choose_tiles(P, HW), HW, c.d, with_fit != 0,
+                           beta_per_particle(c));
+}
+
+int gl_model_plan(const gl_model* m, int P, gl_plan* out) {
+  clear_error();
+  if (!m || !out) return set_error(GL_E_INVALID, "NULL argument");
+  if (P < 1) return set_error(GL_E_INVALID, "P must be >= 1");
+  const ModelCfg& c = m->sys.cfg;
+  const int HW = c.H * c.W;
+  const int tiles = choose_tiles(P, HW);
+  const SysDesc s = make_sys(m->sys, m->ws, P, tiles);
+  out->psf_path = s.conv_mfma ? GL_PSF_MFMA : (s.bands > 1 ? GL_PSF_BANDED : GL_PSF_VALU);
+  out->tiles = s.tiles;
+  out->fwd_tiles = s.ftiles;
+  out->bands = s.bands;
+  out->workspace_bytes = workspace_bytes(P, acc_rows_upto(P, HW), HW, c.d, false,
+                                         beta_per_particle(c));
+  out->workspace_reserved = m->ws.bytes;
   return GL_OK;
 }
 

@@ -182,10 +182,162 @@ GL_HD void series_step(int n, double t, double& ratio, double& dlog) {
 // of dc_n / dt = c_n sum_k dlog_k, given the running product and sum.
 GL_HD void series_store(PConst& c, int n, double cn, double dsum) {
   c.c[n] = n < c.nterms ? cn : 0.0;
-  c.cf[n] = n < c.nterms_d ? float(cn) : 0.f;
   c.dc[n] = n < c.nterms_d ? float(cn * dsum) : 0.f;
   if (n > 0) c.nc[n - 1] = n < c.nterms_d ? float(n * cn) : 0.f;
   if (n == kMaxTerms - 1) c.nc[kMaxTerms - 1] = 0.f;
+}
+
+// ------------------------------------------------------------------------------------------
+// The floored sub-pixel. The elliptical mass radius R is kept >= 1e-6 arcsec (R^2 >= 1e-12);
+// below that the deflection is the formula with R frozen at 1e-6, a function of the remaining
+// variables whose derivatives the per-lane FP32 adjoint does not carry (the frozen radius on
+// |w| is 1e-12 (1 + |eps|)^2, which depends on eps, and the SIE's closed form with a frozen
+// radius is not its series with one). The prologue finds that sub-pixel (at most one per
+// particle) and evaluates the frozen-radius deflection and its derivatives exactly, by
+// forward-mode dual numbers in FP64 over (t, eps1, eps2, x_c, y_c).
+// ------------------------------------------------------------------------------------------
+struct D5 {
+  double v;
+  double d[5];
+};
+GL_HD D5 d5(double v, int k = -1) {
+  D5 r;
+  r.v = v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = i == k ? 1.0 : 0.0;
+  return r;
+}
+GL_HD D5 operator+(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v + b.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+GL_HD D5 operator-(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v - b.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+GL_HD D5 operator*(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v * b.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+GL_HD D5 operator*(double s, const D5& a) {
+  D5 r;
+  r.v = s * a.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = s * a.d[i];
+  return r;
+}
+GL_HD D5 operator/(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v / b.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+  return r;
+}
+// f(a) given f(a.v) and f'(a.v)
+GL_HD D5 d5_chain(const D5& a, double f, double df) {
+  D5 r;
+  r.v = f;
+  for (int i = 0; i < 5; ++i) r.d[i] = df * a.d[i];
+  return r;
+}
+GL_HD D5 d5_exp(const D5& a) { const double e = exp(a.v); return d5_chain(a, e, e); }
+GL_HD D5 d5_log(const D5& a) { return d5_chain(a, log(a.v), 1.0 / a.v); }
+GL_HD D5 d5_sqrt(const D5& a) { const double r = sqrt(a.v); return d5_chain(a, r, 0.5 / r); }
+GL_HD D5 d5_atan(const D5& a) { return d5_chain(a, atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
+GL_HD D5 d5_atanh(const D5& a) { return d5_chain(a, atanh(a.v), 1.0 / (1.0 - a.v * a.v)); }
+GL_HD D5 d5_cos(const D5& a) { return d5_chain(a, cos(a.v), -sin(a.v)); }
+GL_HD D5 d5_sin(const D5& a) { return d5_chain(a, sin(a.v), cos(a.v)); }
+GL_HD D5 d5_atan2(const D5& y, const D5& x) {
+  D5 r;
+  r.v = atan2(y.v, x.v);
+  const double n = x.v * x.v + y.v * y.v;
+  for (int i = 0; i < 5; ++i) r.d[i] = (x.v * y.d[i] - y.v * x.d[i]) / n;
+  return r;
+}
+
+// Centre of sub-pixel column (or row) n of the system's grid: x0 + n dxs, one rounding.
+GL_HD double subpix_coord(double x0, int n, double dxs) { return fma(double(n), dxs, x0); }
+
+// Deflection at image position (x, y) with the elliptical radius frozen at its floor
+// R_f = 1e-6 arcsec, as dual numbers over (t, eps1, eps2, x_c, y_c).
+//   EPL (and the SIE's series): alpha = A w S_t(X) with A = (theta_E sqrt(q) / R_f)^t,
+//     q = (1 - |eps|)/(1 + |eps|), w = z - eps conj(z), X = conj(eps) w^2 / |w_f|^2,
+//     |w_f| = R_f (1 + |eps|): the series form in which |w| only enters through R;
+//   SIE: the closed form with the radius frozen, in the lens frame (rotation by
+//     phi = atan2(eps2, eps1) / 2): alpha_l = b / q' (atan(q' x_l / R_f), atanh(q' y_l / R_f)),
+//     b = theta_E sqrt(q), q' = sqrt(1 - q^2); at |eps| = 0 the SIS limit b z / R_f.
+// |eps| has no derivative at eps = 0: there the eps-derivatives of |eps| are taken as 0.
+GL_HD void floored_deflection(const PConst& c, int mass, double x, double y, D5& ar, D5& ai) {
+  const double rf = 1e-6;
+  const D5 e1 = d5(c.e1, 1), e2 = d5(c.e2, 2);
+  const D5 zr = d5(x) - d5(c.xc, 3), zi = d5(y) - d5(c.yc, 4);
+  const D5 ee = e1 * e1 + e2 * e2;
+  const D5 ea = ee.v > 0.0 ? d5_sqrt(ee) : d5(0.0);
+  const D5 one = d5(1.0);
+  const D5 q = (one - ea) / (one + ea);
+  const double the = double(c.theta_e);
+  if (mass == 1) {
+    const D5 t = d5(c.t, 0);
+    const D5 A = d5_exp(t * (d5(log(the / rf)) + 0.5 * d5_log(q)));
+    const D5 wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
+    const D5 wf2 = (rf * rf) * ((one + ea) * (one + ea));
+    const D5 w2r = wr * wr - wi * wi, w2i = 2.0 * (wr * wi);
+    const D5 Xr = (e1 * w2r + e2 * w2i) / wf2, Xi = (e1 * w2i - e2 * w2r) / wf2;
+    D5 Sr = one, Si = d5(0.0), cn = one, pr = one, pi = d5(0.0);
+    for (int n = 1; n < c.nterms; ++n) {
+      cn = cn * (d5(2.0 * n - 2.0) + t) / (d5(2.0 * n + 2.0) - t);
+      const D5 nr = d5(0.0) - (pr * Xr - pi * Xi), ni = d5(0.0) - (pr * Xi + pi * Xr);
+      pr = nr;
+      pi = ni;
+      Sr = Sr + cn * pr;
+      Si = Si + cn * pi;
+    }
+    ar = A * (wr * Sr - wi * Si);
+    ai = A * (wr * Si + wi * Sr);
+    return;
+  }
+  const D5 b = the * d5_sqrt(q);
+  if (ea.v == 0.0) {  // circular: the SIS with its radius frozen
+    ar = (1.0 / rf) * (b * zr);
+    ai = (1.0 / rf) * (b * zi);
+    return;
+  }
+  const D5 phi = 0.5 * d5_atan2(e2, e1);
+  const D5 cp = d5_cos(phi), sp = d5_sin(phi);
+  const D5 xl = cp * zr + sp * zi, yl = sp * (d5(0.0) - zr) + cp * zi;
+  const D5 qp = d5_sqrt(one - q * q);
+  const D5 axl = b / qp * d5_atan((1.0 / rf) * (qp * xl));
+  const D5 ayl = b / qp * d5_atanh((1.0 / rf) * (qp * yl));
+  ar = cp * axl - sp * ayl;
+  ai = sp * axl + cp * ayl;
+}
+
+// Finds the floored sub-pixel of one particle (fills c.fl_*; after decode_mass). Only the
+// sub-pixel nearest the lens centre can have R below the floor.
+GL_HD void decode_floor(const SysDesc& s, PConst& c) {
+  c.fl_i = c.fl_j = -1;
+  c.fl_a[0] = c.fl_a[1] = 0.0;
+  const double fj = rint((c.xc - s.x0) / s.dxs), fi = rint((c.yc - s.y0) / s.dxs);
+  if (!(fj >= 0.0 && fj < double(s.W * s.k) && fi >= 0.0 && fi < double(s.H * s.k))) return;
+  const int jj = int(fj), ii = int(fi);
+  const double x = subpix_coord(s.x0, jj, s.dxs), y = subpix_coord(s.y0, ii, s.dxs);
+  const double zr = x - c.xc, zi = y - c.yc;
+  const double wr = zr - c.e1 * zr - c.e2 * zi, wi = zi - c.e2 * zr + c.e1 * zi;
+  if (!(wr * wr + wi * wi < c.w2floor)) return;
+  D5 ar, ai;
+  floored_deflection(c, s.mass, x, y, ar, ai);
+  c.fl_i = ii;
+  c.fl_j = jj;
+  c.fl_a[0] = ar.v;
+  c.fl_a[1] = ai.v;
+  for (int k = 0; k < 5; ++k) {
+    c.fl_d[k][0] = ar.d[k];
+    c.fl_d[k][1] = ai.d[k];
+  }
 }
 
 // Light constants (lens light, source Sersic, shapelet coefficients) of one vector.
@@ -320,15 +472,16 @@ struct MassState {
   float A;            // B^t |w|^-t
   Cx S, XSX, U2SX, St;  // S_t(X), X dS/dX, u2 dS/dX, dS/dt
   Cx alpha;
-  int floored;        // |w|^2 hit the floor
 };
 
 // EPL / SIE deflection plus shear at image position (x, y), in FP64: returns beta - x_s with
 // beta = x - alpha - alpha_ext. cs: the particle's series coefficients c.c (the kernels pass
 // a copy staged in LDS).
+// at_floor: this is the particle's floored sub-pixel (c.fl_*); the SIE then takes the
+// frozen-radius closed form the prologue evaluated (the EPL's value there is this formula's).
 template <int MASS>
 GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, double y,
-                     float& sdx, float& sdy) {
+                     bool at_floor, float& sdx, float& sdy) {
   const double zr = x - c.xc, zi = y - c.yc;
   const double e1 = c.e1, e2 = c.e2;
   const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
@@ -375,7 +528,11 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, d
     Si = yi * b2;
     A = exp_f64(c.tlnb - 0.5 * c.t * log_f64(w2));
   }
-  const double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
+  double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
+  if (MASS == 0 && at_floor) {
+    ar = c.fl_a[0];
+    ai = c.fl_a[1];
+  }
   // beta - x_s = x - alpha - alpha_ext - x_s
   sdx = float(x - ar - (c.g1 * x + c.g2 * y) - c.sxs);
   sdy = float(y - ai - (c.g2 * x - c.g1 * y) - c.sys);
@@ -394,18 +551,18 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, d
 //         cancels like |eps|, costing at most a relative 1e-6 / 0.02), by its series below;
 //   dS/dt (EPL) by its series; the series run over the FP32-resolution length nterms_d;
 //   log and exp are the hardware ones.
-// cfs / ncs / dcs: the particle's c.cf / c.nc / c.dc (staged in LDS).
+// |w|^2 is kept at or above the floor so that every quantity stays finite; the particle's
+// floored sub-pixel itself (c.fl_*) takes its mass terms from the prologue's exact
+// derivatives instead (the caller passes a zero weight here).
+// ncs / dcs: the particle's c.nc / c.dc (staged in LDS).
 template <int MASS>
-__device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ cfs,
-                                                  const float* __restrict__ ncs,
+__device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ ncs,
                                                   const float* __restrict__ dcs, double x,
                                                   double y, float sdx, float sdy, MassState& m) {
   const float zr = float(x) - c.xcf, zi = float(y) - c.ycf;
   const float e1 = c.e1f, e2 = c.e2f;
   const float wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
-  float w2 = wr * wr + wi * wi;
-  m.floored = w2 < c.w2floorf;
-  w2 = m.floored ? c.w2floorf : w2;
+  const float w2 = fmaxf(wr * wr + wi * wi, c.w2floorf);
   const float inv_w2 = rcp_f32(w2);
   const float u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0f * wr * wi * inv_w2;
   const float Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
@@ -452,22 +609,10 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
       }
     }
   }
-  float Sr, Si;
-  if (!m.floored) {
-    // S = alpha conj(w) / (A |w|^2)
-    const float r = rcp_f32(A * w2);
-    Sr = (ar * wr + ai * wi) * r;
-    Si = (ai * wr - ar * wi) * r;
-  } else {
-    float b1 = 0.f, b2 = 0.f;
-    for (int n = nd4 - 1; n >= 0; --n) {
-      const float b0 = fmaf(r2, b1, fmaf(-yy, b2, cfs[n]));
-      b2 = b1;
-      b1 = b0;
-    }
-    Sr = fmaf(-yr, b2, b1);
-    Si = yi * b2;
-  }
+  // S = alpha conj(w) / (A |w|^2)
+  const float r = rcp_f32(A * w2);
+  const float Sr = (ar * wr + ai * wi) * r;
+  const float Si = (ai * wr - ar * wi) * r;
   if (sx_series) {
     const Cx SX = {-fmaf(-yr, d2, d1), -yi * d2};  // dS/dX = -dS/dy
     m.XSX = cmul(m.X, SX);
@@ -513,12 +658,8 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
 template <int MASS>
 GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, Cx g, float* acc) {
   const Cx XSX = m.XSX;
-  Cx P1 = cadd(cscale(m.S, c.hp), XSX);  // (1 - t/2) S + X S_X
-  Cx P2 = csub(cscale(m.S, c.hm), XSX);  // -(t/2) S - X S_X
-  if (m.floored) {  // |w|^2 frozen at the floor: X = conj(eps) w^2 / floor
-    P1 = cadd(m.S, cscale(XSX, 2.0f));
-    P2 = {0.f, 0.f};
-  }
+  const Cx P1 = cadd(cscale(m.S, c.hp), XSX);  // (1 - t/2) S + X S_X
+  const Cx P2 = csub(cscale(m.S, c.hm), XSX);  // -(t/2) S - X S_X
   const Cx gA = {g.r * m.A, -g.i * m.A};  // A gb
   const Cx U = cmul(gA, P1);
   const Cx V = cmul(gA, cmul(m.u2, P2));
@@ -542,11 +683,6 @@ GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, C
 }
 
 // Elliptical Sersic intensity at offset (dx, dy) from its centre.
-struct LightEval {
-  float I, E, rho, lnrho, IQ, Q;
-  int floored;
-};
-
 GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
   // R^2 = dx (qa dx + qb dy) + qc dy^2
   float q = fmaf(dx, fmaf(L.qb, dy, L.qa * dx), L.qc * dy * dy);
@@ -668,6 +804,47 @@ GL_HD void shapelet_adj(const PConst& c, float sdx, float sdy, const float* shp,
   acc[A_SHP_BETA] += (-U - u * Iu - v * Iv) * ib;
   gbx = Iu * ib;
   gby = Iv * ib;
+}
+
+// d(source Sersic + shapelets)/d(beta) at offset (sdx, sdy) from the source centre, in FP64
+// (the floored sub-pixel's weight g of the mass terms, formed once per particle):
+//   Sersic: dI/dR^2 = -I b_n rho / (2 n R^2), rho = (R / R_eff)^(1/n), dR^2 = 2 (px, py);
+//   shapelets: as shapelet_adj, with g_n' = n g_(n-1).
+GL_HD void source_light_grad(const PConst& c, int nmax, double sdx, double sdy, double& gx,
+                             double& gy) {
+  const LightC& L = c.src;
+  const double px = L.qa * sdx + 0.5 * double(L.qb) * sdy;
+  const double py = L.qc * sdy + 0.5 * double(L.qb) * sdx;
+  const double r2 = sdx * px + sdy * py;
+  gx = gy = 0.0;
+  if (r2 >= kR2FloorD) {
+    const double n = L.n, rho = exp(log(r2) / (2.0 * n) - log(double(L.re)) / n);
+    const double I = double(L.i0) * exp(double(L.bn) * (1.0 - rho));
+    const double dIdr2 = -I * double(L.bn) * rho / (2.0 * n * r2);
+    gx = 2.0 * dIdr2 * px;
+    gy = 2.0 * dIdr2 * py;
+  }
+  if (nmax < 0) return;
+  const double ib = c.inv_beta, u = sdx * ib, v = sdy * ib;
+  double hu[kMaxNmax + 1], hv[kMaxNmax + 1];
+  hu[0] = hv[0] = 1.0;
+  hu[1] = u;
+  hv[1] = v;
+  for (int k = 1; k < nmax; ++k) {
+    hu[k + 1] = u * hu[k] - 0.5 * k * hu[k - 1];
+    hv[k + 1] = v * hv[k] - 0.5 * k * hv[k - 1];
+  }
+  double U = 0.0, Uu = 0.0, Uv = 0.0;
+  for (int n1 = 0; n1 <= nmax; ++n1)
+    for (int n2 = 0; n1 + n2 <= nmax; ++n2) {
+      const double ck = c.shp[shp_index(n1, n2)];
+      U += ck * hu[n1] * hv[n2];
+      if (n1 > 0) Uu += ck * n1 * hu[n1 - 1] * hv[n2];
+      if (n2 > 0) Uv += ck * n2 * hu[n1] * hv[n2 - 1];
+    }
+  const double G = exp(-0.5 * (u * u + v * v));
+  gx += G * (Uu - u * U) * ib;
+  gy += G * (Uv - v * U) * ib;
 }
 
 // ------------------------------------------------------------------------------------------

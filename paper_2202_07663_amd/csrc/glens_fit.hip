@@ -143,13 +143,6 @@ int validate_fit_opts(const gl_fit_opts* o, int d, std::vector<Prior>& pri) {
   return GL_OK;
 }
 
-#define GL_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
-                       #call, hipGetErrorString(e_));                                    \
-  } while (0)
 
 FitParams fit_params(const gl_fit_opts* o) {
   FitParams f;
@@ -262,6 +255,16 @@ struct gl_fit_state {
   FitParams fp;
 };
 
+// The model's work space at this fit's size with the fit buffers (a likelihood call on the
+// same model between two fit calls may have regrown it).
+static int fit_reserve(gl_fit_state* st) {
+  gl_model* m = st->model;
+  const ModelCfg& c = m->sys.cfg;
+  const int HW = c.H * c.W;
+  return workspace_reserve(m->ws, st->fp.P, choose_tiles(st->fp.P, HW), HW, c.d, true,
+                           beta_per_particle(c));
+}
+
 static SysDesc fit_sys(gl_fit_state* st) {
   gl_model* m = st->model;
   const int tiles = choose_tiles(st->fp.P, m->sys.cfg.H * m->sys.cfg.W);
@@ -323,6 +326,10 @@ int gl_fit_state_step(gl_fit_state* st, int n, void* stream) {
   if (n < 0) return set_error(GL_E_INVALID, "n must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   const ModelCfg& c = st->model->sys.cfg;
+  if (n > 0) {
+    int rc = fit_reserve(st);
+    if (rc) return rc;
+  }
   for (int i = 0; i < n; ++i) {
     Group g;
     std::memset(&g, 0, sizeof(g));
@@ -375,11 +382,13 @@ int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream) {
   if (!st || !out) return set_error(GL_E_INVALID, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
   const ModelCfg& c = st->model->sys.cfg;
+  int rc = fit_reserve(st);
+  if (rc) return rc;
   Group g;
   std::memset(&g, 0, sizeof(g));
   g.nsys = 1;
   g.sys[0] = fit_sys(st);
-  int rc = run_group(g, subpix_key(c), c.K, 1, s);
+  rc = run_group(g, subpix_key(c), c.K, 1, s);
   if (!rc) rc = launch_logpost(g, s);
   if (rc) return rc;
   return fit_result_from_device(st->fb, st->model->ws, st->fp.P, c, s, out);

@@ -15,6 +15,19 @@ namespace glens {
 int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 
+// Return GL_E_NOMEM / GL_E_DEVICE with a message when a HIP call fails. The runtime's
+// last-error state is cleared on the way, so that a later launch check (hipGetLastError)
+// does not report this failure again.
+#define GL_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      (void)hipGetLastError();                                                           \
+      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
+                       #call, hipGetErrorString(e_));                                    \
+    }                                                                                    \
+  } while (0)
+
 // Validated copy of a model descriptor (host pointers dropped).
 struct ModelCfg {
   int H, W, k, K;
@@ -28,7 +41,8 @@ int nparams(int mass, int shear, int lens_light, int nmax);
 
 // Device work space of one system for P particles.
 struct Workspace {
-  int cap_P = 0, cap_tiles = 0, HW = 0;
+  int cap_P = 0, HW = 0;
+  size_t cap_rows = 0;     // accumulator rows (particle x tile) of acc
   PConst* pc = nullptr;
   float* m0 = nullptr;
   float* sbar = nullptr;
@@ -42,8 +56,15 @@ struct Workspace {
   int beta_pp = 0;         // its float2 entries per particle
   size_t bytes = 0;
 };
-// beta_pp: float2 entries of the beta buffer per particle (beta_per_particle(cfg)).
-size_t workspace_bytes(int P, int tiles, int HW, int d, bool fit_buffers, int beta_pp);
+// beta_pp: float2 entries of the beta buffer per particle (beta_per_particle(cfg)); rows:
+// accumulator rows, P x tiles for one batch size (acc_rows_upto for every size up to P).
+size_t workspace_bytes(int P, size_t rows, int HW, int d, bool fit_buffers, int beta_pp);
+size_t acc_rows_upto(int P, int HW);
+// Carve the work space out of `base` (workspace_bytes long, 256-byte aligned).
+void workspace_layout(Workspace& ws, char* base, int P, size_t rows, int HW, int d,
+                      bool fit_buffers, int beta_pp);
+// Grow ws (owned allocation) to hold a batch of P particles split into `tiles` tiles; a
+// growth synchronises the device and reallocates, keeping the fit buffers once present.
 int workspace_reserve(Workspace& ws, int P, int tiles, int HW, int d, bool fit_buffers,
                       int beta_pp);
 void workspace_free(Workspace& ws);

@@ -49,7 +49,10 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
   }
   __syncthreads();
   PConst& c = s.pc[p];
-  if (lane == 0) decode_mass(th, s.mass, s.shear, c);
+  if (lane == 0) {
+    decode_mass(th, s.mass, s.shear, c);
+    decode_floor(s, c);
+  }
   if (lane == 1) decode_lights(th, s.mass, s.shear, s.lens_light, s.nmax, c);
   const double t = (s.mass == 1) ? double(th[1]) - 1.0 : 1.0;
   if (lane > 0 && lane < kMaxTerms) series_step(lane, t, s_ratio[lane], s_dlog[lane]);
@@ -74,20 +77,20 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
 // ------------------------------------------------------------------------------------------
 // Copies the particle's series coefficients to LDS (read uniformly by every lane).
 __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float* s_nc,
-                                             float* s_dc, float* s_cf = nullptr) {
+                                             float* s_dc) {
   for (int n = threadIdx.x; n < kMaxTerms; n += blockDim.x) {
     s_c[n] = c.c[n];
     s_nc[n] = c.nc[n];
     s_dc[n] = c.dc[n];
-    if (s_cf) s_cf[n] = c.cf[n];
   }
   __syncthreads();
 }
 
 template <int MASS, int LL, int NMAX>
 __device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
-                                                    double y, const float* shp, float2& sd) {
-  ray_trace<MASS>(c, s_c, x, y, sd.x, sd.y);
+                                                    double y, bool at_floor, const float* shp,
+                                                    float2& sd) {
+  ray_trace<MASS>(c, s_c, x, y, at_floor, sd.x, sd.y);
   float v = sersic_fwd(c.src, sd.x, sd.y);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, sd.x, sd.y, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
@@ -118,11 +121,13 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
     const int i = pix / W, j = pix - i * W;
     float sum = 0.f;
     for (int a = 0; a < k; ++a) {
-      const double y = s.y0 + double(i * k + a) * s.dxs;
+      const double y = subpix_coord(s.y0, i * k + a, s.dxs);
       for (int b = 0; b < k; ++b) {
-        const double x = s.x0 + double(j * k + b) * s.dxs;
+        const double x = subpix_coord(s.x0, j * k + b, s.dxs);
+        // the SIE's floored sub-pixel takes the prologue's frozen-radius deflection
+        const bool at_floor = MASS == 0 && i * k + a == c->fl_i && j * k + b == c->fl_j;
         float2 sd;
-        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, shp, sd);
+        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, at_floor, shp, sd);
         if (beta) {  // streamed past the caches: read once, by the adjoint, much later
           float* bp = reinterpret_cast<float*>(beta + (a * k + b) * (s.H * W) + pix);
           __builtin_nontemporal_store(sd.x, bp);
@@ -779,8 +784,8 @@ subpix_adj_kernel(Group g) {
   const int part = lb / s.tiles, tile = lb - part * s.tiles;
   const PConst& c = s.pc[part];
   __shared__ double s_c[kMaxTerms];
-  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms], s_cf[kMaxTerms];
-  stage_series(c, s_c, s_nc, s_dc, s_cf);
+  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
+  stage_series(c, s_c, s_nc, s_dc);
   // beta - x_s from the forward pass (kept there for gradient calls)
   const float2* beta = s.beta + (size_t)part * s.k * s.k * s.H * s.W;
   const int HW = s.H * s.W, W = s.W, k = s.k;
@@ -803,12 +808,12 @@ subpix_adj_kernel(Group g) {
     const int i = pix / W, j = pix - i * W;
     const float sb = sbar[pix];
     for (int a = 0; a < k; ++a) {
-      const double y = s.y0 + double(i * k + a) * s.dxs;
+      const double y = subpix_coord(s.y0, i * k + a, s.dxs);
       for (int b = 0; b < k; ++b) {
-        const double x = s.x0 + double(j * k + b) * s.dxs;
+        const double x = subpix_coord(s.x0, j * k + b, s.dxs);
         MassState m;
         const float* bp = reinterpret_cast<const float*>(beta + (a * k + b) * HW + pix);
-        mass_jacobian_f32<MASS>(c, s_cf, s_nc, s_dc, x, y, __builtin_nontemporal_load(bp),
+        mass_jacobian_f32<MASS>(c, s_nc, s_dc, x, y, __builtin_nontemporal_load(bp),
                                 __builtin_nontemporal_load(bp + 1), m);
         // gx, gy: sb d(source light)/d(beta)
         float gx, gy;
@@ -827,7 +832,11 @@ subpix_adj_kernel(Group g) {
           acc[A_LENS + L_DX] += lx;
           acc[A_LENS + L_DY] += ly;
         }
-        mass_adjoint<MASS>(c, m, float(x), float(y), Cx{gx, gy}, acc);
+        // the floored sub-pixel's mass terms are added by finalize from the prologue's
+        // exact derivatives
+        const bool at_floor = i * k + a == c.fl_i && j * k + b == c.fl_j;
+        mass_adjoint<MASS>(c, m, float(x), float(y),
+                           at_floor ? Cx{0.f, 0.f} : Cx{gx, gy}, acc);
       }
     }
   }
@@ -861,11 +870,36 @@ __global__ void __launch_bounds__(64) finalize_kernel(Group g) {
     a[q] = v;
   }
   __syncthreads();
+  const PConst& c = s.pc[p];
+  if (threadIdx.x == 0 && c.fl_i >= 0) {
+    // the floored sub-pixel: g = sbar d(source light)/d(beta) there (FP64), contracted with
+    // the prologue's exact deflection derivatives; shear terms as the main loop forms them
+    const int k = s.k, HW = s.H * s.W;
+    const int pi = c.fl_i / k, pj = c.fl_j / k, sub = (c.fl_i - pi * k) * k + (c.fl_j - pj * k);
+    const int pix = pi * s.W + pj;
+    const double sb = s.sbar[(size_t)p * HW + pix];
+    const float2 bs = s.beta[((size_t)p * k * k + sub) * HW + pix];
+    double gx, gy;
+    source_light_grad(c, s.nmax, bs.x, bs.y, gx, gy);
+    gx *= sb;
+    gy *= sb;
+    a[A_M_ALPHA] += gx * c.fl_a[0] + gy * c.fl_a[1];
+    a[A_M_T] += gx * c.fl_d[0][0] + gy * c.fl_d[0][1];
+    a[A_M_E1] += gx * c.fl_d[1][0] + gy * c.fl_d[1][1];
+    a[A_M_E2] += gx * c.fl_d[2][0] + gy * c.fl_d[2][1];
+    a[A_M_X] -= gx * c.fl_d[3][0] + gy * c.fl_d[3][1];  // d/dx = -d/dx_c
+    a[A_M_Y] -= gx * c.fl_d[4][0] + gy * c.fl_d[4][1];
+    const double x = float(subpix_coord(s.x0, c.fl_j, s.dxs));
+    const double y = float(subpix_coord(s.y0, c.fl_i, s.dxs));
+    a[A_M_G1] += gx * x - gy * y;
+    a[A_M_G2] += gx * y + gy * x;
+  }
+  __syncthreads();
   // lane 0 maps the sums (to LDS, not to a lane-private array the compiler would spill);
   // the lanes then check and store the components
   __shared__ float gr[kMaxParams];
   __shared__ int s_j;
-  if (threadIdx.x == 0) s_j = map_gradient(s.pc[p], a, s.mass, s.shear, s.lens_light, s.nmax, gr);
+  if (threadIdx.x == 0) s_j = map_gradient(c, a, s.mass, s.shear, s.lens_light, s.nmax, gr);
   __syncthreads();
   const int j = s_j;
   int bad = 0;

@@ -59,6 +59,7 @@ struct Active {
   FitBuffers fb;
   int tiles = 1;
   uint64_t t_admit = 0;
+  int failed = GL_OK;  // first error of a launch on this system; it then retires with it
 };
 
 static double request_work(const ModelCfg& c, int P) {
@@ -69,7 +70,7 @@ static size_t request_bytes(const ModelCfg& c, int P) {
   const int HW = c.H * c.W;
   const size_t psf_tab = c.K <= kMfmaMaxK ? size_t(2) * c.K * 64 * 16 * sizeof(uint16_t) : 0;
   return sizeof(float) * (2 * c.K * c.K + HW) + psf_tab +
-         workspace_bytes(P, choose_tiles(P, HW), HW, c.d, true, beta_per_particle(c)) +
+         workspace_bytes(P, acc_rows_upto(P, HW), HW, c.d, true, beta_per_particle(c)) +
          fit_buffers_bytes(P, c.d);
 }
 
@@ -93,7 +94,6 @@ struct gl_server {
   gl_server_stats st{};
   std::vector<std::unique_ptr<Active>> active;  // scheduler thread only
   double active_work = 0.0;                      // scheduler thread only
-  int thread_error = 0;
 };
 
 static void finish(gl_server* s, Active& a, const gl_fit_result& r) {
@@ -102,6 +102,22 @@ static void finish(gl_server* s, Active& a, const gl_fit_result& r) {
   s->pending.erase(a.req->ticket);
   s->st.completed++;
   s->st.hbm_in_use -= a.req->bytes;
+  if (r.status != GL_OK) {
+    s->st.failed++;
+    s->st.last_error = r.status;
+  }
+}
+
+static gl_fit_result error_result(const Active& a, int rc) {
+  gl_fit_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.status = rc;
+  r.d = a.req->cfg.d;
+  r.best = -1;
+  r.t_submit = a.req->t_submit;
+  r.t_admit = a.t_admit;
+  r.t_done = now_ns();
+  return r;
 }
 
 static void release(Active& a) {
@@ -120,32 +136,31 @@ static int admit(gl_server* s, std::unique_ptr<Request> rq) {
   if (!rc) rc = workspace_reserve(a->ws, rq->fp.P, a->tiles, HW, c.d, true, beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(a->fb, rq->fp.P, c.d, rq->priors.data());
   a->req = std::move(rq);
-  if (rc) {
-    gl_fit_result r;
-    std::memset(&r, 0, sizeof(r));
-    r.status = rc;
-    r.d = c.d;
-    r.best = -1;
-    r.t_submit = a->req->t_submit;
-    r.t_admit = a->t_admit;
-    r.t_done = now_ns();
+  if (!rc) {
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.nsys = 1;
+    g.sys[0] = make_sys(a->sys, a->ws, a->req->fp.P, a->tiles);
+    attach_fit(g.sys[0], a->fb, a->req->fp, a->ws);
+    rc = launch_fit_init(g, s->stream);
+  }
+  if (rc) {  // retired at once with the error; the stream has no work of it in flight
     s->active_work -= a->req->work;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) rc = GL_E_DEVICE;
+    const gl_fit_result r = error_result(*a, rc);
     release(*a);
     finish(s, *a, r);
     return rc;
   }
-  Group g;
-  std::memset(&g, 0, sizeof(g));
-  g.nsys = 1;
-  g.sys[0] = make_sys(a->sys, a->ws, a->req->fp.P, a->tiles);
-  attach_fit(g.sys[0], a->fb, a->req->fp, a->ws);
-  rc = launch_fit_init(g, s->stream);
   s->active.push_back(std::move(a));
-  return rc;
+  return GL_OK;
 }
 
-// Systems grouped by kernel configuration; each group runs `mode` and, for mode 2, Adam.
+// Systems grouped by kernel configuration; each group runs `mode` and, for mode 2, Adam. A
+// group whose launches fail marks its systems (they retire with the error at the end of the
+// tick); the other groups go on.
 static int run_grouped(gl_server* s, std::vector<Active*>& sys, int mode) {
+  int first_rc = GL_OK;
   std::map<std::pair<int, int>, std::vector<Active*>> by_key;
   for (Active* a : sys) by_key[{subpix_key(a->req->cfg), a->req->cfg.K}].push_back(a);
   for (auto& kv : by_key) {
@@ -162,10 +177,14 @@ static int run_grouped(gl_server* s, std::vector<Active*>& sys, int mode) {
       int rc = run_group(g, kv.first.first, kv.first.second, mode, s->stream);
       if (!rc && mode == 2) rc = launch_adam(g, s->stream);
       if (!rc && mode == 1) rc = launch_logpost(g, s->stream);
-      if (rc) return rc;
+      if (rc) {
+        for (int i = 0; i < g.nsys; ++i)
+          if (list[i0 + i]->failed == GL_OK) list[i0 + i]->failed = rc;
+        if (first_rc == GL_OK) first_rc = rc;
+      }
     }
   }
-  return GL_OK;
+  return first_rc;
 }
 
 static void tick(gl_server* s) {
@@ -186,40 +205,50 @@ static void tick(gl_server* s) {
       s->st.queued = int(s->queue.size());
     }
     s->active_work += rq->work;
-    admit(s, std::move(rq));
+    admit(s, std::move(rq));  // a failure retires the request with its status
   }
   if (s->active.empty()) return;
   // 2. advance every active system by up to steps_per_tick steps
   for (int k = 0; k < s->opts.steps_per_tick; ++k) {
     std::vector<Active*> run;
     for (auto& a : s->active)
-      if (a->req->fp.step < a->req->fp.K) run.push_back(a.get());
+      if (a->failed == GL_OK && a->req->fp.step < a->req->fp.K) run.push_back(a.get());
     if (run.empty()) break;
-    if (run_grouped(s, run, 2)) s->thread_error = 1;
-    for (Active* a : run) a->req->fp.step++;
+    run_grouped(s, run, 2);
+    for (Active* a : run)
+      if (a->failed == GL_OK) a->req->fp.step++;
   }
-  // 3. retire finished systems
+  // 3. retire finished and failed systems
+  auto done = [](const Active& a) { return a.failed != GL_OK || a.req->fp.step >= a.req->fp.K; };
   std::vector<Active*> fin;
   for (auto& a : s->active)
-    if (a->req->fp.step >= a->req->fp.K) fin.push_back(a.get());
-  if (!fin.empty() && run_grouped(s, fin, 1)) s->thread_error = 1;
-  if (hipStreamSynchronize(s->stream) != hipSuccess) s->thread_error = 1;
-  for (Active* a : fin) {
+    if (a->failed == GL_OK && a->req->fp.step >= a->req->fp.K) fin.push_back(a.get());
+  if (!fin.empty()) run_grouped(s, fin, 1);
+  if (hipStreamSynchronize(s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    for (auto& a : s->active)
+      if (a->failed == GL_OK) a->failed = GL_E_DEVICE;
+  }
+  for (auto& ap : s->active) {
+    Active* a = ap.get();
+    if (!done(*a)) continue;
     s->active_work -= a->req->work;
     gl_fit_result r;
-    std::memset(&r, 0, sizeof(r));
-    int rc = fit_result_from_device(a->fb, a->ws, a->req->fp.P, a->req->cfg, s->stream, &r);
-    if (rc) r.status = rc;
-    r.t_submit = a->req->t_submit;
-    r.t_admit = a->t_admit;
-    r.t_done = now_ns();
+    if (a->failed != GL_OK) {
+      r = error_result(*a, a->failed);
+    } else {
+      std::memset(&r, 0, sizeof(r));
+      int rc = fit_result_from_device(a->fb, a->ws, a->req->fp.P, a->req->cfg, s->stream, &r);
+      if (rc) r.status = rc;
+      r.t_submit = a->req->t_submit;
+      r.t_admit = a->t_admit;
+      r.t_done = now_ns();
+    }
     release(*a);
     finish(s, *a, r);
   }
   s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
-                                 [](const std::unique_ptr<Active>& a) {
-                                   return a->req->fp.step >= a->req->fp.K;
-                                 }),
+                                 [&](const std::unique_ptr<Active>& a) { return done(*a); }),
                   s->active.end());
   std::lock_guard<std::mutex> lk(s->mu);
   s->st.ticks++;

@@ -13,6 +13,10 @@ constexpr int kMaxShp = (kMaxNmax + 1) * (kMaxNmax + 2) / 2;  // 45
 constexpr int kMaxParams = 68;
 constexpr int kNAcc = 72;          // adjoint accumulator slots per (particle, tile)
 constexpr float kR2Floor = 1e-12f; // arcsec^2 floor on elliptical radii
+constexpr double kR2FloorD = 1e-12;
+// Smallest sub-pixel pitch (arcsec): a mass radius below the floor needs the sub-pixel within
+// 4e-6 arcsec of the lens centre (|eps| <= 0.6), so at most one sub-pixel can be floored.
+constexpr double kMinPitch = 1e-4;
 constexpr float kMassEpsMax = 0.6f;
 constexpr float kLightEpsMax = 0.9f;
 constexpr float kSieClosedMin = 0.1f;  // SIE closed form for |eps| >= this, series below
@@ -70,6 +74,15 @@ struct PConst {
   double sr, si;       // SIE closed form: s = sqrt(conj(eps))
   double epsabs;
   double c[kMaxTerms]; // series coefficients c_n(t)
+  // The sub-pixel, if any, where the elliptical mass radius sits at its floor (the lens
+  // centre within ~1e-6 arcsec of a sub-pixel centre; at most one, as sub-pixels are at least
+  // kMinPitch apart): its row and column on the sub-pixel grid (-1: none), the deflection
+  // there as the floored formula gives it, and its derivatives d alpha / d (t, eps1, eps2,
+  // x_c, y_c) (clamped eccentricities), all FP64. The adjoint adds that sub-pixel's mass terms
+  // from these instead of from its per-lane Jacobian.
+  int fl_i, fl_j;
+  double fl_a[2];
+  double fl_d[5][2];
   double sxs, sys;     // source centre
   double lxs, lys;     // lens-light centre
   // FP32 part
@@ -86,7 +99,6 @@ struct PConst {
   LightC lens, src;
   float beta, inv_beta;
   float shp[kMaxShp];  // c_k r_n1 r_n2 / (beta sqrt(pi)), r_n = sqrt(2^n / n!)
-  float cf[kMaxTerms]; // c_n in FP32 (zero from nterms_d on), for the adjoint's Jacobian
   float dc[kMaxTerms]; // d c_n / dt (zero from nterms_d on)
   float nc[kMaxTerms]; // (n + 1) c_{n+1}: coefficients of dS/dy (zero from nterms_d - 1 on)
 };
@@ -145,7 +157,8 @@ struct SysDesc {
 // PSF pass on matrix cores (v_mfma_f32_16x16x32_f16, operands scaled and split into two fp16
 // parts): for each PSF row a the output tile
 // [16 rows x N columns] += (image rows shifted by a, a 32-column window) x (the 32 x 16
-// Toeplitz matrix T_a[kk][n] = psf[a][kk - n]). N = min(16, 33 - K) columns fit the window.
+// Toeplitz matrix T_a[kk][n] = psf[a][kk - n]). N = min(16, 33 - K), rounded down to a
+// multiple of 4, columns fit the window.
 constexpr int kMfmaMaxK = 21;       // largest PSF for this pass
 constexpr int kMfmaWaveTiles = 16;  // output tiles per wave (4 waves: <= 64 tiles per image)
 
@@ -158,7 +171,12 @@ struct MfmaGeom {
 };
 __host__ __device__ inline MfmaGeom mfma_geom(int H, int W, int K) {
   MfmaGeom q;
-  q.N = 33 - K < 16 ? 33 - K : 16;
+  // a multiple of 4, so that every tile's fragment offset (tile column tc N, lane group 8 g,
+  // row pitch) is a multiple of four fp16 and the 8-byte LDS fragment reads stay aligned
+  // (K <= 21 gives N >= 12; the geometry of larger PSFs, which never take this pass, keeps
+  // N >= 1)
+  const int n = 33 - K < 16 ? 33 - K : 16;
+  q.N = n >= 4 ? n & ~3 : (n < 1 ? 1 : n);
   q.TR = (H + 15) / 16;
   q.TC = (W + q.N - 1) / q.N;
   q.T = q.TR * q.TC;

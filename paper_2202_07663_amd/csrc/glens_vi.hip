@@ -187,13 +187,6 @@ __global__ void __launch_bounds__(256) vi_dense_kernel(const double* x, int d, d
 
 using namespace glens;
 
-#define GL_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return set_error(e_ == hipErrorOutOfMemory ? GL_E_NOMEM : GL_E_DEVICE, "%s: %s",   \
-                       #call, hipGetErrorString(e_));                                    \
-  } while (0)
 
 struct gl_vi {
   gl_model* model = nullptr;

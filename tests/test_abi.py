@@ -68,6 +68,8 @@ def test_null_arguments(lib):
     assert lib.gl_loglik(None, None, 4, None, None) == -1
     assert lib.gl_loglik_grad(None, None, 4, None, None, None) == -1
     assert lib.gl_simulate(None, None, 4, None, None) == -1
+    assert lib.gl_model_reserve(None, 4, 0) == -1
+    assert lib.gl_model_plan(None, 4, None) == -1
     assert lib.gl_model_destroy(None) == 0
     assert b"NULL" in lib.gl_last_error() or lib.gl_last_error() == b""
 

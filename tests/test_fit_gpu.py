@@ -177,3 +177,54 @@ def test_fit_recovers_the_truth(G):
     _say("K=1000 chi2nu", r["chi2nu"], "theta_E", r["theta_best"][0])
     assert r["chi2nu"] < 1.01
     assert abs(r["theta_best"][0] - truth[0]) < 1e-3 * truth[0]
+
+
+def test_fit_state_survives_a_workspace_regrow(G):
+    """Plain likelihood calls between two fit calls on the same model, one on a single
+    vector (many tiles per vector) and one on a batch larger than the fit's, regrow the
+    model's work space; the fit buffers are kept and the fit state's next steps and result
+    use the regrown work space. They equal those of an undisturbed twin state."""
+    spec = synth.spec_c1()
+    obs, truth = load_workload(spec.name)
+    priors = synth.fit_priors(spec)
+    P = 64
+    m1 = G.Model.from_spec(spec, obs)
+    m2 = G.Model.from_spec(spec, obs)
+    a = G.FitState(m1, P, 20, priors, seed=31)
+    b = G.FitState(m2, P, 20, priors, seed=31)
+    a.step(2)
+    b.step(2)
+    before = m1.plan(1)["workspace_reserved"]
+    for n in (1, 8192):
+        th = torch.from_numpy(synth.draw_particles(spec, truth, n, seed=2)).cuda()
+        m1.loglik(th)
+        m1.loglik_grad(th)
+    torch.cuda.synchronize()
+    after = m1.plan(1)["workspace_reserved"]
+    _say("work space", before, "->", after)
+    assert after > before
+    a.step(3)
+    b.step(3)
+    ra, rb = a.result(), b.result()
+    assert ra["status"] == 0 and rb["status"] == 0
+    np.testing.assert_array_equal(a.store()[0].cpu().numpy(), b.store()[0].cpu().numpy())
+    assert ra["best"] == rb["best"] and ra["logpost_best"] == rb["logpost_best"]
+
+
+def test_reserve_keeps_calls_from_growing(G):
+    """gl_model_reserve sizes the work space for every batch size up to P: later likelihood
+    and fit calls at or below P leave it as it is."""
+    spec = synth.spec_c1()
+    obs, truth = load_workload(spec.name)
+    m = G.Model.from_spec(spec, obs)
+    m.reserve(512, with_fit=True)
+    held = m.plan(1)["workspace_reserved"]
+    assert held >= m.plan(512)["workspace_bytes"]
+    for P in (1, 3, 64, 333, 512):
+        th = torch.from_numpy(synth.draw_particles(spec, truth, P, seed=P)).cuda()
+        m.loglik_grad(th)
+        assert m.plan(1)["workspace_reserved"] == held
+    st = G.FitState(m, 512, 5, synth.fit_priors(spec), seed=1)
+    st.step(5)
+    assert st.result()["status"] == 0
+    assert m.plan(1)["workspace_reserved"] == held

@@ -143,13 +143,15 @@ def test_ragged_configs(glens, case):
     assert err.max() < 2e-5, err.max()
 
 
-@pytest.mark.parametrize("eps", [0.0005, 0.0199, 0.0201, 0.05, 0.0999, 0.1001, 0.3, 0.55, 0.7])
+@pytest.mark.parametrize("eps", [1e-6, 1e-4, 0.0005, 0.0199, 0.0201, 0.05, 0.0999, 0.1001, 0.3,
+                                 0.55, 0.7])
 @pytest.mark.parametrize("epl", [False, True])
 def test_mass_ellipticity_range(glens, eps, epl):
     """Both SIE branches (series below |eps| = 0.1, closed form above), both ways of getting
     the series derivative dS/dX in the adjoint (its own series below |eps| = 0.02, the
-    first-order identity above), the EPL series up to its longest expansion, and the |eps|
-    clamp at 0.6."""
+    first-order identity above), the EPL series up to its longest expansion, the |eps|
+    clamp at 0.6, and nearly round lenses (|eps| = 1e-6, 1e-4), where the oracle's (q, phi)
+    form is still differentiable (at |eps| = 0 exactly its phi is not)."""
     spec = synth.Spec("e", 32, 32, 2, epl=epl, lens_light=False, nmax=2,
                       psf=synth.moffat_psf(7, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
     truth = synth.draw_truth(spec, 11)
@@ -167,14 +169,16 @@ def test_mass_ellipticity_range(glens, eps, epl):
     assert_grad_close(g, g_ref, names=spec.names)
 
 
+@pytest.mark.parametrize("offset", [(0.0, 0.0), (3e-7, -2e-7), (-6e-7, 1e-7)],
+                         ids=["on", "near1", "near2"])
 @pytest.mark.parametrize("epl", [False, True])
-def test_lens_centre_on_a_sub_pixel(glens, epl):
-    """A lens centre exactly on a sub-pixel, where the elliptical radius sits at its floor on
-    both sides (the adjoint then sums the value series there instead of taking S from alpha).
-    The deflection there is zero, so log L and the light-parameter gradient are defined and
-    compared with the oracle; the mass-parameter gradient takes that sub-pixel's frozen-radius
-    derivative, which the two sides define on different radii, so it is only checked to be
-    finite."""
+def test_lens_centre_on_a_sub_pixel(glens, epl, offset):
+    """A lens centre on, or within 1e-6 arcsec of, a sub-pixel centre: the elliptical radius
+    there sits at its floor (R^2 >= 1e-12) on both sides. Log L and the whole gradient are
+    compared with the oracle, whose derivative there is that of the frozen-radius formula
+    (the SIE's closed form, the EPL's series; the frozen radius carries the eps-dependence
+    of the mass radius). That one sub-pixel's mass Jacobian is ~1e6 times a normal one's, so
+    it dominates the centre and eccentricity gradients."""
     spec = synth.Spec("c", 31, 31, 1, epl=epl, lens_light=False, nmax=2,
                       psf=synth.moffat_psf(7, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
     truth = synth.draw_truth(spec, 12)
@@ -183,14 +187,42 @@ def test_lens_centre_on_a_sub_pixel(glens, epl):
     om = oracle_model(spec)
     obs = synth.add_noise(oracle.simulate(om, truth.astype(np.float64))[0], 12, 0.1, 1000.0)
     theta = synth.draw_particles(spec, truth, 8, seed=3)
-    theta[:, ic] = theta[:, ic + 1] = 0.0
+    theta[:, ic] = np.float32(offset[0])
+    theta[:, ic + 1] = np.float32(offset[1])
+    _say("case centre", epl, offset)
     m = glens.Model.from_spec(spec, obs)
     ll, g = _run(m, theta)
     ll_ref, g_ref = oracle.loglik_grad(om, theta.astype(np.float64), obs)
     assert_logl_close(ll, ll_ref)
-    assert np.all(np.isfinite(g))
-    nm = ic + 2 + 2 * int(spec.shear)  # mass parameters come first
-    assert_grad_close(g[:, nm:], g_ref[:, nm:], names=spec.names[nm:])
+    e = assert_grad_close(g, g_ref, names=spec.names)
+    _say("centre", epl, offset, "grad err", e)
+    img = m.simulate(torch.from_numpy(theta).cuda()).cpu().numpy()
+    ref = oracle.simulate(om, theta.astype(np.float64))
+    assert (np.abs(img - ref) / np.abs(ref).max(axis=(1, 2), keepdims=True)).max() < 2e-5
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-4])
+def test_light_ellipticity_near_round(glens, eps):
+    """Nearly round lens light and source (|eps| = 1e-6, 1e-4): the kernels' rotation-free
+    quadratic form against the oracle's (q, phi) form, which is still differentiable there
+    (at |eps| = 0 exactly its phi is not)."""
+    spec = synth.Spec("l", 36, 36, 2, epl=True, lens_light=True, nmax=3,
+                      psf=synth.moffat_psf(9, 0.15, 2.5), sigma_bkg=0.1, t_exp=1000.0)
+    truth = synth.draw_truth(spec, 13)
+    om = oracle_model(spec)
+    obs = synth.add_noise(oracle.simulate(om, truth.astype(np.float64))[0], 13, 0.1, 1000.0)
+    theta = synth.draw_particles(spec, truth, 8, seed=6)
+    ang = np.linspace(0, 2 * np.pi, 8, endpoint=False) + 0.3
+    il, isrc = 8, 15  # lens light and source (eps1, eps2) follow the 8 mass parameters
+    for i0 in (il + 2, isrc + 2):
+        theta[:, i0] = eps * np.cos(ang)
+        theta[:, i0 + 1] = eps * np.sin(ang)
+    assert spec.names[il + 2] == "l_e1" and spec.names[isrc + 2] == "s_e1"
+    m = glens.Model.from_spec(spec, obs)
+    ll, g = _run(m, theta)
+    ll_ref, g_ref = oracle.loglik_grad(om, theta.astype(np.float64), obs)
+    assert_logl_close(ll, ll_ref)
+    assert_grad_close(g, g_ref, names=spec.names)
 
 
 # ------------------------------------------------------------------------------------------

@@ -119,3 +119,20 @@ def test_unknown_ticket(G):
         srv.poll(12345)
     assert "GL_E_NOTFOUND" in str(e.value)
     srv.close()
+
+
+def test_admission_failure_is_reported(G):
+    """A request the device cannot hold (budget larger than the device, so admission's
+    allocation fails) retires with GL_E_NOMEM; the server counts it and serves the next
+    request normally."""
+    srv = G.Server(hbm_budget_bytes=1 << 50, max_systems=4, steps_per_tick=5)
+    spec, obs = _system(40, 4, True, True, 8, 9)
+    big = srv.submit(spec, obs, 1 << 21, 5, synth.fit_priors(spec), seed=1)  # ~1.6 TB
+    r = srv.wait(big)
+    assert r["status"] == -2, r["status"]
+    ok = srv.wait(_submit(srv, MIX[0], K=5))
+    st = srv.stats()
+    srv.close()
+    assert ok["status"] == 0
+    assert st["failed"] == 1 and st["last_error"] == -2 and st["completed"] == 2
+    assert st["hbm_in_use"] == 0
