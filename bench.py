@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
 SERIES_TOL_FP32 = 6e-8     # series length counted by the op model (FP32 resolution)
+# the kernels behind each stage (rocprofv3 kernel names)
+KERNEL_NAMES = {"subpix_adj": "subpix_adj_kernel", "subpix_fwd": "subpix_fwd_kernel",
+                "conv_lik": "conv_mfma_kernel"}
 
 # ------------------------------------------------------------------------------------------
 # Algorithmic op-count model (frozen; FMA = 2, add / mul / compare = 1, each transcendental
@@ -78,16 +81,60 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def load_profile(workload: str):
+    """The committed rocprofv3 record of this workload (kernel-trace durations, HBM counters
+    scaled by the copy calibration, VALU instruction counters per sub-pixel), or None when
+    the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"record_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("csrc_hash") != csrc_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def executed_flop_per_subpixel(counters: dict) -> float:
+    """FLOP a kernel executes per sub-pixel from its VALU instruction counters (wave
+    instructions x 64 lanes per sub-pixel): FMA = 2, add / mul / transcendental = 1, in FP32
+    and FP64. Moves, conversions, compares and selects are not arithmetic and not counted."""
+    c = counters
+    return (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"]
+            + c["SQ_INSTS_VALU_TRANS_F32"] + 2 * c["SQ_INSTS_VALU_FMA_F64"]
+            + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"])
+
+
+def cpu_info() -> dict:
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+def call_times_ms(fn, n):
+    """Durations of n back-to-back calls (ms), from HIP events on the current stream (the
+    library's kernels run on it)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def spread(ms: np.ndarray, P: int) -> dict:
+    q = np.percentile(ms, [10, 50, 90])
+    return {"calls": int(ms.size), "ms_p10": round(float(q[0]), 4), "ms_median": round(float(q[1]), 4),
+            "ms_p90": round(float(q[2]), 4), "evals_per_s_median": round(P / (q[1] * 1e-3), 1)}
 
 
 def stored(spec, seed=0):
@@ -178,20 +225,39 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     }
 
 
-def cpu_baseline(spec, obs, theta, n_sample: int):
-    """The FP64 oracle (dual-number gradient) on the first n_sample vectors of the same
-    batch, on all host cores it is given."""
+def cpu_baseline(spec, obs, theta, n_sample: int, n_one: int = 8):
+    """The FP64 oracle (dual-number gradient for log L + gradient, plain FP64 for log L alone)
+    on evenly spaced vectors of the same batch: all host cores on n_sample vectors, one core
+    on n_one."""
     import oracle
     from tests.helpers import oracle_model
     om = oracle_model(spec)
     idx = np.linspace(0, theta.shape[0] - 1, n_sample).astype(int)
     th = theta[idx].astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.loglik_grad(om, th, obs)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "logL+grad evals/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"{n_sample} of the 4096 vectors (evenly spaced), same image and model"}
+    cores = oracle.num_threads()
+
+    def timed(fn, x):
+        t0 = time.perf_counter()
+        fn(om, x, obs)
+        return time.perf_counter() - t0
+
+    t_grad = timed(oracle.loglik_grad, th)
+    t_ll = timed(oracle.loglik, th)
+    oracle.set_num_threads(1)
+    try:
+        t_grad1 = timed(oracle.loglik_grad, th[:n_one])
+        t_ll1 = timed(oracle.loglik, th[:4 * n_one])
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": n_sample / t_grad, "unit": "logL+grad evals/s", "cores": cores,
+            "kind": "oracle", "seconds": round(t_grad, 3),
+            "sample": f"{n_sample} of the 4096 vectors (evenly spaced), same image and model",
+            "loglik_only_evals_per_s": round(n_sample / t_ll, 2),
+            "one_core": {"logL+grad_evals_per_s": round(n_one / t_grad1, 3),
+                         "loglik_only_evals_per_s": round(4 * n_one / t_ll1, 2),
+                         "sample": f"the first {n_one} (log L + gradient) and {4 * n_one} "
+                                   "(log L) of those vectors"},
+            **cpu_info()}
 
 
 # ------------------------------------------------------------------------------------------
@@ -307,8 +373,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--spread-calls", type=int, default=200,
+                    help="calls timed one by one for the median / p10 / p90 spread")
     ap.add_argument("--serve-systems", type=int, default=32,
                     help="systems in the serving stream (0 skips the serving measurement)")
     ap.add_argument("--serve-steps", type=int, default=300, help="Adam steps per fit")
@@ -338,6 +406,7 @@ def main():
     P = theta_np.shape[0]
     theta = torch.from_numpy(theta_np).cuda()
     model = G.Model.from_spec(spec, obs)
+    model.reserve(P)
     ll = torch.empty(P, dtype=torch.float64, device="cuda")
     gr = torch.empty((P, model.d), dtype=torch.float32, device="cuda")
 
@@ -353,13 +422,22 @@ def main():
     value = P / (wall / args.steps)
     assert torch.isfinite(ll).all(), "non-finite log-likelihood in the benchmark batch"
 
+    # per-call spread (HIP events) at the benchmark size, at P = 64, and for log L alone
+    grad_ms = call_times_ms(lambda: model.loglik_grad(theta, out=(ll, gr)), args.spread_calls)
+    ll_ms = call_times_ms(lambda: model.loglik(theta, out=ll), args.spread_calls)
+    th64 = theta[:64].contiguous()
+    ll64 = torch.empty(64, dtype=torch.float64, device="cuda")
+    gr64 = torch.empty((64, model.d), dtype=torch.float32, device="cuda")
+    for _ in range(20):
+        model.loglik_grad(th64, out=(ll64, gr64))
+    p64_ms = call_times_ms(lambda: model.loglik_grad(th64, out=(ll64, gr64)), args.spread_calls)
+
     # stage durations with HIP events on the stream the kernels run on
     stages = None
     for _ in range(args.stage_reps):
         st = model.stage_times(theta, with_grad=True)
         stages = st if stages is None else {k: stages[k] + st[k] for k in st}
     stages = {k: v / args.stage_reps for k, v in stages.items()}
-    fwd = model.stage_times(theta, with_grad=False)
 
     eps = np.hypot(theta_np[:, 2], theta_np[:, 3])
     N_mean = float(series_terms(eps).mean())
@@ -369,7 +447,31 @@ def main():
     dominant = max(("subpix_adj", "subpix_fwd", "conv_lik"), key=lambda k: stages[k])
     achieved = per_launch[dominant] / (stages[dominant] * 1e-3) / 1e12
     total_flops = sum(per_launch.values())
-    traffic = load_traffic(dominant, "epl60_P4096")
+    rec = load_profile("epl60_P4096")
+    roof = {"bound": "alu", "kernel": dominant,
+            "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None,
+            "algorithmic_flop_per_launch": per_launch[dominant],
+            "kernel_ms": round(stages[dominant], 4),
+            "peak_unpacked_fp32": PEAK_FP32_TFLOPS / 2,
+            "basis": "achieved = op-model FLOP per launch / kernel time (an effective rate: the "
+                     "kernel executes fewer operations than the model counts)"}
+    if rec is not None:
+        kr = rec["kernels"][KERNEL_NAMES[dominant]]
+        roof["traffic"] = kr.get("hbm_bytes_per_launch")
+        prof_ms = kr["avg_us"] * 1e-3
+        roof["profile_kernel_ms"] = round(prof_ms, 4)
+        roof["frac_profile"] = round(per_launch[dominant] / (prof_ms * 1e-3) / 1e12 /
+                                     PEAK_FP32_TFLOPS, 4)
+        if "valu_per_subpixel" in kr:
+            ex = executed_flop_per_subpixel(kr["valu_per_subpixel"])
+            sub = P * spec.H * spec.W * spec.k ** 2
+            ex_tf = ex * sub / (stages[dominant] * 1e-3) / 1e12
+            roof["executed_flop_per_subpixel"] = round(ex, 1)
+            roof["executed_tflops"] = round(ex_tf, 2)
+            roof["executed_frac"] = round(ex_tf / PEAK_FP32_TFLOPS, 4)
+            roof["valu_busy_profile"] = kr.get("valu_busy")
 
     out = {
         "metric": "logL+grad evals/s (60x60 EPL+shapelets); fits/hour + p50/p99 latency",
@@ -382,20 +484,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64 (PSF on fp16 matrix cores, two-part split)",
         "data": "synthetic",
         "config": {"workload": "epl60_shapelet6_k2_moffat21", "P": P, "d": model.d,
                    "image": [spec.H, spec.W], "k_super": spec.k, "psf": spec.psf.shape[0],
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "alu", "kernel": dominant,
-                     "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic,
-                     "algorithmic_flop_per_launch": per_launch[dominant],
-                     "kernel_ms": round(stages[dominant], 4)},
+        "roofline": roof,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "spread": {"logL+grad_P4096": spread(grad_ms, P), "logL_P4096": spread(ll_ms, P),
+                   "logL+grad_P64": spread(p64_ms, 64)},
         "whole_path_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 2),
-        "loglik_only_ms": round(sum(fwd.values()), 4),
         "flop_per_eval": round(total_flops / P),
         "series_terms_counted": round(N_mean, 2),
     }
@@ -403,14 +501,12 @@ def main():
         out["serving"] = serving_bench(args.serve_systems, args.serve_steps)
     if not args.no_pipeline:
         import synth
+        out["c4_pipeline"] = dict(workload="epl60_s0", **pipeline_bench(
+            spec, *stored(spec, 0), n_map=4096, k_map=300, n_vi=1000, k_vi=1000, chains=64,
+            L=10, n_burn=250, n_samples=750, adapt_length=False))
         sp = synth.spec_paper80()
         out["pipeline"] = dict(workload="paper80_s6", **pipeline_bench(
             sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=1000, chains=50, L=5))
-        # the same system with a longer surrogate fit and longer chains (Table 1's VI budget
-        # leaves the surrogate widths at 0.1-0.6 of the posterior's here)
-        out["pipeline_long"] = dict(workload="paper80_s6", **pipeline_bench(
-            sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=6000, chains=50, L=5,
-            n_burn=1000, n_samples=1000, vi_lr=3e-3, vi_warmup=300, vi_init_sd=3e-3))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
     print(json.dumps(_finite(out), allow_nan=False), flush=True)
