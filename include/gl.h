@@ -111,11 +111,13 @@ int gl_model_reserve(gl_model* model, int P, int with_fit);
  *   tiles, fwd_tiles: sub-pixel work tiles per vector of the adjoint and the forward pass;
  *   bands:     row bands of the PSF pass (1 unless banded);
  *   workspace_bytes: device work space of a likelihood call at this P (gl_model_reserve);
- *   workspace_reserved: what the model holds now. */
+ *   workspace_reserved: what the model holds now;
+ *   noalloc_max_P: the largest P gl_loglik_grad_noalloc accepts on this model. */
 enum { GL_PSF_MFMA = 0, GL_PSF_VALU = 1, GL_PSF_BANDED = 2 };
 typedef struct gl_plan {
   int psf_path, tiles, fwd_tiles, bands;
   size_t workspace_bytes, workspace_reserved;
+  int noalloc_max_P;
 } gl_plan;
 int gl_model_plan(const gl_model* model, int P, gl_plan* out);
 
@@ -138,6 +140,20 @@ int gl_loglik(gl_model* model, const float* theta, int P, double* logl, void* st
  * adjoint of every step). grad: device [P][d] FP32 (written). */
 int gl_loglik_grad(gl_model* model, const float* theta, int P, double* logl, float* grad,
                    void* stream);
+
+/* gl_loglik_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results (bitwise, for the same P), with the work space taken from a fixed array of
+ * 128 MiB that the library holds on every device it runs on until the process ends, instead
+ * of the model's own allocation. The call allocates nothing and never grows anything; it
+ * enqueues work on `stream` and returns.
+ *   Limit: P up to gl_plan.noalloc_max_P of the model (about 800 vectors at 60 x 60 pixels
+ *   and k_super = 2); a larger P returns GL_E_BUDGET with the sizes in gl_last_error().
+ *   The array is shared by every call on one device and keeps the last call's contents:
+ *   calls that overlap on one device (other streams, other threads) race, so the caller
+ *   orders them. The current device must be the model's (GL_E_INVALID otherwise). */
+int gl_loglik_grad_noalloc(gl_model* model, const float* theta, int P, double* logl,
+                           float* grad, void* stream);
 
 /* Diagnostic: run the gl_loglik_grad pipeline (with_grad = 1) or the gl_loglik pipeline
  * (with_grad = 0) once on `stream` with HIP events between its kernels, wait for it, and

@@ -128,7 +128,8 @@ class Model:
         check(lib().gl_model_plan(self._h, int(P), ctypes.byref(r)))
         return {"psf_path": self.PSF_PATHS[r.psf_path], "tiles": r.tiles,
                 "fwd_tiles": r.fwd_tiles, "bands": r.bands,
-                "workspace_bytes": r.workspace_bytes, "workspace_reserved": r.workspace_reserved}
+                "workspace_bytes": r.workspace_bytes, "workspace_reserved": r.workspace_reserved,
+                "noalloc_max_P": r.noalloc_max_P}
 
     def simulate(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
         theta = self._theta(theta)

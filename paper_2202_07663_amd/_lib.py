@@ -95,7 +95,7 @@ GL_PSF_MFMA, GL_PSF_VALU, GL_PSF_BANDED = 0, 1, 2
 class Plan(ctypes.Structure):
     _fields_ = [("psf_path", ctypes.c_int), ("tiles", ctypes.c_int), ("fwd_tiles", ctypes.c_int),
                 ("bands", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
-                ("workspace_reserved", ctypes.c_size_t)]
+                ("workspace_reserved", ctypes.c_size_t), ("noalloc_max_P", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -109,6 +109,7 @@ _SIGNATURES = {
     "gl_simulate": [_vp, _vp, _i, _vp, _vp],
     "gl_loglik": [_vp, _vp, _i, _vp, _vp],
     "gl_loglik_grad": [_vp, _vp, _i, _vp, _vp, _vp],
+    "gl_loglik_grad_noalloc": [_vp, _vp, _i, _vp, _vp, _vp],
     "gl_model_stage_times": [_vp, _vp, _i, _i, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp],
     "gl_fit": [_vp, ctypes.POINTER(FitOpts), ctypes.POINTER(FitResult), _vp],
     "gl_fit_state_create": [_vp, ctypes.POINTER(FitOpts), ctypes.POINTER(_vp), _vp],

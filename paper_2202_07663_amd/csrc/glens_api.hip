@@ -609,6 +609,7 @@ int gl_model_plan(const gl_model* m, int P, gl_plan* out) {
   out->workspace_bytes = workspace_bytes(P, acc_rows_upto(P, HW), HW, c.d, false,
                                          beta_per_particle(c));
   out->workspace_reserved = m->ws.bytes;
+  out->noalloc_max_P = noalloc_max_particles(c);
   return GL_OK;
 }
 
