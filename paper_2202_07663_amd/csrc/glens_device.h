@@ -369,22 +369,14 @@ GL_HD void decode_lights(const float* th, int mass, int shear, int lens_light, i
 // ------------------------------------------------------------------------------------------
 // Double-precision helpers for the ray trace, for the argument ranges met there (normal,
 // finite, positive arguments). Written from the mathematics:
-//   rcp: hardware estimate refined by two Newton steps r <- r (2 - x r);
-//   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m-1)/(m+1),
-//        |s| <= 0.172, summed to s^11 (absolute truncation < 2e-11);
-//   exp: x = k ln2 + r with |r| <= ln2/2 (Cody-Waite reduction, ln2 as a double plus its
-//        tail), e^r by its Taylor series to r^10 (relative truncation < 3e-13), then scaled
-//        by 2^k.
+//   rcp: hardware estimate (relative error about 2^-23) refined by one Newton step
+//        r <- r + r (1 - x r), which squares the error (about 1e-14);
+//   the power B^t |w|^-t: per-particle tables (pow_from_table, after these helpers).
 // The targets sit below the 1e-10 relative tolerance of the deflection series: the ray
 // trace needs |alpha| to ~1e-9 arcsec, far below FP32 resolution but far above FP64's.
 // ------------------------------------------------------------------------------------------
-constexpr double kLn2 = 0.6931471805599453;        // nearest double to ln 2
-constexpr double kLn2Tail = 2.3190468138462996e-17;  // ln 2 - kLn2
-constexpr double kInvLn2 = 1.4426950408889634;
-
 __device__ __forceinline__ double rcp_f64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
+  const double r = __builtin_amdgcn_rcp(x);
   return fma(fma(-x, r, 1.0), r, r);
 }
 __host__ inline double rcp_f64(double x) { return 1.0 / x; }
@@ -400,53 +392,41 @@ __host__ inline float rcp_f32(float x) { return 1.0f / x; }
 constexpr float kLn2f = 0.69314718055994531f;
 constexpr float kLog2e = 1.44269504088896341f;
 
-// A compile-time constant placed in scalar registers. In the polynomial loops below the
-// compiler would otherwise keep the FP64 coefficients in vector registers across the
-// sub-pixel loop and copy each into the accumulator of a two-operand FMA (an extra vector
-// move per term, and ~30 vector registers held). An empty asm statement that takes the
-// value in scalar registers makes it a scalar operand. Not volatile: the statement may be
-// moved and merged like any computation (a volatile one pins the schedule and costs more
-// than it saves).
-__device__ __forceinline__ double sconst(double c) {
-  asm("" : "+s"(c));
-  return c;
-}
-__host__ inline double sconst(double c) { return c; }
+constexpr double kLn2 = 0.6931471805599453;  // nearest double to ln 2
 
-GL_HD double log_f64(double x) {
-  int e;
-  double m = frexp(x, &e);  // [0.5, 1)
-  if (m < 0.70710678118654752) {
-    m *= 2.0;
-    e -= 1;
-  }
-  const double s = (m - 1.0) * rcp_f64(m + 1.0);
-  const double s2 = s * s;
-  double p = 1.0 / 11.0;
-  p = fma(p, s2, sconst(1.0 / 9.0));
-  p = fma(p, s2, sconst(1.0 / 7.0));
-  p = fma(p, s2, sconst(1.0 / 5.0));
-  p = fma(p, s2, sconst(1.0 / 3.0));
-  p = fma(p, s2, 1.0);
-  const double de = double(e);
-  return fma(de, kLn2, fma(de, kLn2Tail, 2.0 * s * p));
+// Entries of the power tables (PConst::pw) at table index i: i < kPowExp gives B^t 2^(-t e/2)
+// for e = i - kPowExp/2; i = kPowExp + 8 j + k the Taylor coefficient k of m^(-t/2) about
+// m_j = 1 + (j + 1/2)/16: a_0 = m_j^(-t/2), a_k = a_(k-1) (-t/2 - k + 1) / (k m_j).
+GL_HD double pow_table_entry(double t, double log2B, int i) {
+  if (i < kPowExp) return exp2(t * (log2B - 0.5 * (i - kPowExp / 2)));
+  const int j = (i - kPowExp) / 8, k = (i - kPowExp) % 8;
+  if (k > kPowDeg) return 0.0;
+  const double mj = 1.0 + (j + 0.5) / kPowSeg;
+  double a = exp2(-0.5 * t * log2(mj));
+  for (int q = 1; q <= k; ++q) a *= (-0.5 * t - (q - 1)) / (q * mj);
+  return a;
 }
 
-GL_HD double exp_f64(double x) {
-  const double k = rint(x * kInvLn2);
-  const double r = fma(-k, kLn2Tail, fma(-k, kLn2, x));
-  double p = 1.0 / 3628800.0;  // 1/10!
-  p = fma(p, r, sconst(1.0 / 362880.0));
-  p = fma(p, r, sconst(1.0 / 40320.0));
-  p = fma(p, r, sconst(1.0 / 5040.0));
-  p = fma(p, r, sconst(1.0 / 720.0));
-  p = fma(p, r, sconst(1.0 / 120.0));
-  p = fma(p, r, sconst(1.0 / 24.0));
-  p = fma(p, r, sconst(1.0 / 6.0));
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  return ldexp(p, int(k));
+// A = B^t |w|^-t = B^t (|w|^2)^(-t/2) from the particle's power tables (staged in LDS): with
+// |w|^2 = 2^e m, m in [1, 2), the four leading mantissa bits pick the sixteenth j of [1, 2)
+// and the remaining ones give x = m - m_j exactly, so that A = T[e] P_j(x) (about 3e-11
+// relative; no logarithm or exponential). |w|^2 is at least the 1e-12 floor, so e >= -40; an
+// exponent beyond the table (|w| above 2^31 arcsec) is clamped.
+GL_HD double pow_from_table(const double* __restrict__ pw, double w2) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, w2);
+  const int e = int((b >> 52) & 0x7ffu) - 1023;
+  const int j = int((b >> 48) & 15u);
+  const double m = __builtin_bit_cast(double, (b & 0x0000ffffffffffffull) | 0x3ff0000000000000ull);
+  const double x = m - (1.0 + 0.5 / kPowSeg);
+  const double* a = pw + kPowExp + 8 * j;
+  double p = fma(a[6], x, a[5]);
+  p = fma(p, x, a[4]);
+  p = fma(p, x, a[3]);
+  p = fma(p, x, a[2]);
+  p = fma(p, x, a[1]);
+  p = fma(p, x, a[0]);
+  const int ie = e + kPowExp / 2;
+  return pw[ie < 0 ? 0 : (ie >= kPowExp ? kPowExp - 1 : ie)] * p;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -479,9 +459,11 @@ struct MassState {
 // a copy staged in LDS).
 // at_floor: this is the particle's floored sub-pixel (c.fl_*); the SIE then takes the
 // frozen-radius closed form the prologue evaluated (the EPL's value there is this formula's).
+// cs / pw: the particle's series coefficients c.c and power tables c.pw (staged in LDS).
 template <int MASS>
-GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, double y,
-                     bool at_floor, float& sdx, float& sdy) {
+GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs,
+                     const double* __restrict__ pw, double x, double y, bool at_floor,
+                     float& sdx, float& sdy) {
   const double zr = x - c.xc, zi = y - c.yc;
   const double e1 = c.e1, e2 = c.e2;
   const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
@@ -526,7 +508,7 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs, double x, d
     }
     Sr = fma(-yr, b2, b1);
     Si = yi * b2;
-    A = exp_f64(c.tlnb - 0.5 * c.t * log_f64(w2));
+    A = pow_from_table(pw, w2);
   }
   double ar = A * (wr * Sr - wi * Si), ai = A * (wr * Si + wi * Sr);
   if (MASS == 0 && at_floor) {

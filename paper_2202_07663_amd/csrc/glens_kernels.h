@@ -70,6 +70,9 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
   }
   __syncthreads();
   if (lane < kMaxTerms) series_store(c, lane, s_cn[lane], s_ds[lane]);
+  // power tables of the ray trace (c.t and c.bmass were written by lane 0 before the barrier)
+  const double log2B = log2(c.bmass), tt = c.t;
+  for (int i = lane; i < kPowExp + kPowSeg * 8; i += 64) c.pw[i] = pow_table_entry(tt, log2B, i);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -87,10 +90,11 @@ __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float
 }
 
 template <int MASS, int LL, int NMAX>
-__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c, double x,
-                                                    double y, bool at_floor, const float* shp,
+__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c,
+                                                    const double* s_pw, double x, double y,
+                                                    bool at_floor, const float* shp,
                                                     float2& sd) {
-  ray_trace<MASS>(c, s_c, x, y, at_floor, sd.x, sd.y);
+  ray_trace<MASS>(c, s_c, s_pw, x, y, at_floor, sd.x, sd.y);
   float v = sersic_fwd(c.src, sd.x, sd.y);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, sd.x, sd.y, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
@@ -104,7 +108,8 @@ __device__ __forceinline__ float surface_brightness(const PConst& c, const doubl
 template <int MASS, int LL, int NMAX>
 // beta (or null): where beta - x_s of each sub-pixel is kept for the adjoint, [k^2][H][W].
 __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* __restrict__ c,
-                                               const double* s_c, float* __restrict__ out,
+                                               const double* s_c, const double* s_pw,
+                                               float* __restrict__ out,
                                                float2* __restrict__ beta, int p0, int p1) {
   const int W = s.W, k = s.k;
   // shapelet coefficients held in vector registers for the whole loop (an empty asm with a
@@ -127,7 +132,7 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
         // the SIE's floored sub-pixel takes the prologue's frozen-radius deflection
         const bool at_floor = MASS == 0 && i * k + a == c->fl_i && j * k + b == c->fl_j;
         float2 sd;
-        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, x, y, at_floor, shp, sd);
+        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, s_pw, x, y, at_floor, shp, sd);
         if (beta) {  // streamed past the caches: read once, by the adjoint, much later
           float* bp = reinterpret_cast<float*>(beta + (a * k + b) * (s.H * W) + pix);
           __builtin_nontemporal_store(sd.x, bp);
@@ -148,12 +153,14 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const PConst& c = s.pc[part];
   __shared__ double s_c[kMaxTerms];
   __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
-  stage_series(c, s_c, s_nc, s_dc);
+  __shared__ double s_pw[kPowExp + kPowSeg * 8];
+  for (int i = threadIdx.x; i < kPowExp + kPowSeg * 8; i += blockDim.x) s_pw[i] = c.pw[i];
+  stage_series(c, s_c, s_nc, s_dc);  // its barrier also covers the power tables
   const int HW = s.H * s.W;
   const int p0 = tile * s.fpix_per_tile;
   const int p1 = min(HW, p0 + s.fpix_per_tile);
   float2* beta = s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW : nullptr;
-  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s.m0 + (size_t)part * HW, beta, p0, p1);
+  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s_pw, s.m0 + (size_t)part * HW, beta, p0, p1);
 }
 
 // ------------------------------------------------------------------------------------------

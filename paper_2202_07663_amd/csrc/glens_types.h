@@ -8,6 +8,11 @@
 namespace glens {
 
 constexpr int kMaxTerms = 48;      // EPL series terms (|eps| <= 0.6 needs 47 at the tolerance)
+// Power tables of the ray trace's A = B^t |w|^-t (PConst::pw): exponents e of |w|^2 = 2^e m
+// from -kPowExp/2 to kPowExp/2 - 1, and kPowSeg polynomial segments of m in [1, 2).
+constexpr int kPowExp = 128;
+constexpr int kPowSeg = 16;
+constexpr int kPowDeg = 6;
 constexpr int kMaxNmax = 8;        // shapelet order
 constexpr int kMaxShp = (kMaxNmax + 1) * (kMaxNmax + 2) / 2;  // 45
 constexpr int kMaxParams = 68;
@@ -74,6 +79,12 @@ struct PConst {
   double sr, si;       // SIE closed form: s = sqrt(conj(eps))
   double epsabs;
   double c[kMaxTerms]; // series coefficients c_n(t)
+  // A = B^t |w|^-t of the ray trace, with |w|^2 = 2^e m, m in [1, 2):
+  //   pw[e + kPowExp/2] = B^t 2^(-t e / 2) (e clamped to the table),
+  //   pw[kPowExp + 8 j + k] = coefficient k of the Taylor polynomial of m^(-t/2) about
+  //   m_j = 1 + (j + 1/2)/16, in x = m - m_j, on the sixteenth of [1, 2) that holds m
+  //   (degree 6: truncation below 3e-11 relative for 0 < t < 2)
+  double pw[kPowExp + kPowSeg * 8];
   // The sub-pixel, if any, where the elliptical mass radius sits at its floor (the lens
   // centre within ~1e-6 arcsec of a sub-pixel centre; at most one, as sub-pixels are at least
   // kMinPitch apart): its row and column on the sub-pixel grid (-1: none), the deflection
@@ -152,6 +163,16 @@ struct SysDesc {
   float* seed;           // [P][H][W] adjoint seed (banded PSF pass)
   float2* beta;          // [P][k^2][H][W] beta - x_s of the forward pass (gradient calls)
   double* lpart;         // [P][max bands][2] log L and chi^2 partial sums per band
+  struct FitOut* fit_out;  // result of a served fit (fit_best_kernel), or null
+};
+
+// Result of one fit, formed on the device so that it can be copied to the host without
+// waiting on the stream: the best particle by log posterior (-1: none finite) and its values.
+struct FitOut {
+  int best;
+  int pad;
+  double logl, logpost, chi2;
+  float theta[kMaxParams], z[kMaxParams];
 };
 
 // PSF pass on matrix cores (v_mfma_f32_16x16x32_f16, operands scaled and split into two fp16
