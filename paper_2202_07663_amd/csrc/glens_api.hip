@@ -110,63 +110,89 @@ static uint16_t f16_bits(_Float16 h) {
   return u;
 }
 
-int system_upload(const gl_model_desc* d, const ModelCfg& cfg, SystemData& sd) {
-  sd.cfg = cfg;
-  const int KK = cfg.K * cfg.K, HW = cfg.H * cfg.W;
-  std::vector<float> flip(KK);
-  for (int a = 0; a < cfg.K; ++a)
-    for (int b = 0; b < cfg.K; ++b) flip[a * cfg.K + b] = d->psf[(cfg.K - 1 - a) * cfg.K + (cfg.K - 1 - b)];
-  GL_HIP(hipMalloc(&sd.psf, sizeof(float) * KK));
-  GL_HIP(hipMalloc(&sd.psf_flip, sizeof(float) * KK));
-  GL_HIP(hipMemcpy(sd.psf, d->psf, sizeof(float) * KK, hipMemcpyHostToDevice));
-  GL_HIP(hipMemcpy(sd.psf_flip, flip.data(), sizeof(float) * KK, hipMemcpyHostToDevice));
-  size_t tab_bytes = 0;
-  if (cfg.K <= kMfmaMaxK) {
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// The device image of a system's fixed inputs, in the layout system_bind expects: the PSF,
+// the flipped PSF, for K <= kMfmaMaxK the Toeplitz operands of the matrix-core PSF pass, and
+// the observed image (zeros when there is none), each 256-byte aligned.
+void system_image(const gl_model_desc* d, const ModelCfg& cfg, std::vector<uint8_t>& img,
+                  int* psf_mfma_exp) {
+  const int K = cfg.K, KK = K * K, HW = cfg.H * cfg.W;
+  const size_t o_flip = align256(sizeof(float) * KK);
+  const size_t o_tab = o_flip + align256(sizeof(float) * KK);
+  const size_t tab_bytes = cfg.K <= kMfmaMaxK ? sizeof(uint16_t) * size_t(2) * K * 64 * 16 : 0;
+  const size_t o_obs = o_tab + align256(tab_bytes);
+  img.assign(o_obs + align256(sizeof(float) * HW), 0);
+  float* psf = reinterpret_cast<float*>(img.data());
+  float* flip = reinterpret_cast<float*>(img.data() + o_flip);
+  std::memcpy(psf, d->psf, sizeof(float) * KK);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) flip[a * K + b] = d->psf[(K - 1 - a) * K + (K - 1 - b)];
+  *psf_mfma_exp = 0;
+  if (tab_bytes) {
     // Toeplitz operands of the matrix-core PSF pass, per direction (0: flipped PSF, forward;
     // 1: PSF, adjoint), PSF row a and lane l = n + 16 g: elements e = 0..7 of column n,
     // rows 8g + e, of T_a[kk][n] = psf[a][kk - n] 2^t (zero outside 0 <= kk - n < K, n < N),
     // as two fp16 parts (v = h + l, l from the exact FP32 remainder); 2^t brings the largest
     // tap into [2^14, 2^15).
-    const int K = cfg.K, N = mfma_geom(cfg.H, cfg.W, K).N;
+    const int N = mfma_geom(cfg.H, cfg.W, K).N;
     float pmax = 0.f;
     for (int i = 0; i < KK; ++i) pmax = std::max(pmax, std::fabs(d->psf[i]));
     int e = 0;
     if (pmax > 0.f) std::frexp(pmax, &e);
-    sd.psf_mfma_exp = pmax > 0.f ? 15 - e : 0;
-    std::vector<uint16_t> tab(size_t(2) * K * 64 * 16, 0);
+    const int sx = pmax > 0.f ? 15 - e : 0;
+    *psf_mfma_exp = sx;
+    uint16_t* tab = reinterpret_cast<uint16_t*>(img.data() + o_tab);
     for (int dir = 0; dir < 2; ++dir) {
-      const float* kf = dir == 0 ? flip.data() : d->psf;
+      const float* kf = dir == 0 ? flip : d->psf;
       for (int a = 0; a < K; ++a)
         for (int l = 0; l < 64; ++l)
           for (int e8 = 0; e8 < 8; ++e8) {
             const int n = l % 16, b = 8 * (l / 16) + e8 - n;
-            const float v = (n < N && b >= 0 && b < K) ? std::ldexp(kf[a * K + b], sd.psf_mfma_exp)
-                                                       : 0.f;
+            const float v = (n < N && b >= 0 && b < K) ? std::ldexp(kf[a * K + b], sx) : 0.f;
             const size_t o = ((size_t(dir) * K + a) * 64 + l) * 16;
             const _Float16 h = static_cast<_Float16>(v);
             tab[o + e8] = f16_bits(h);
             tab[o + 8 + e8] = f16_bits(static_cast<_Float16>(v - static_cast<float>(h)));
           }
     }
-    tab_bytes = sizeof(uint16_t) * tab.size();
-    GL_HIP(hipMalloc(&sd.psf_mfma, tab_bytes));
-    GL_HIP(hipMemcpy(sd.psf_mfma, tab.data(), tab_bytes, hipMemcpyHostToDevice));
   }
-  sd.has_obs = d->obs != nullptr;
-  GL_HIP(hipMalloc(&sd.obs, sizeof(float) * HW));
-  if (d->obs) GL_HIP(hipMemcpy(sd.obs, d->obs, sizeof(float) * HW, hipMemcpyHostToDevice));
-  else GL_HIP(hipMemset(sd.obs, 0, sizeof(float) * HW));
-  sd.bytes = sizeof(float) * (2 * KK + HW) + tab_bytes;
+  if (d->obs) std::memcpy(img.data() + o_obs, d->obs, sizeof(float) * HW);
+}
+
+// Points sd at a device copy of system_image (base, img_bytes long).
+void system_bind(SystemData& sd, const ModelCfg& cfg, char* base, size_t img_bytes, int has_obs,
+                 int psf_mfma_exp) {
+  const int KK = cfg.K * cfg.K;
+  const size_t o_flip = align256(sizeof(float) * KK);
+  const size_t o_tab = o_flip + align256(sizeof(float) * KK);
+  const size_t tab_bytes = cfg.K <= kMfmaMaxK ? sizeof(uint16_t) * size_t(2) * cfg.K * 64 * 16 : 0;
+  sd.cfg = cfg;
+  sd.base = base;
+  sd.psf = reinterpret_cast<float*>(base);
+  sd.psf_flip = reinterpret_cast<float*>(base + o_flip);
+  sd.psf_mfma = tab_bytes ? reinterpret_cast<uint4*>(base + o_tab) : nullptr;
+  sd.obs = reinterpret_cast<float*>(base + o_tab + align256(tab_bytes));
+  sd.psf_mfma_exp = psf_mfma_exp;
+  sd.has_obs = has_obs;
+  sd.bytes = img_bytes;
+}
+
+int system_upload(const gl_model_desc* d, const ModelCfg& cfg, SystemData& sd) {
+  std::vector<uint8_t> img;
+  int sx = 0;
+  system_image(d, cfg, img, &sx);
+  char* base = nullptr;
+  GL_HIP(hipMalloc(&base, img.size()));
+  system_bind(sd, cfg, base, img.size(), d->obs != nullptr, sx);
+  sd.owned = true;
+  GL_HIP(hipMemcpy(base, img.data(), img.size(), hipMemcpyHostToDevice));
   return GL_OK;
 }
 
 void system_free(SystemData& sd) {
-  if (sd.psf) (void)hipFree(sd.psf);
-  if (sd.psf_flip) (void)hipFree(sd.psf_flip);
-  if (sd.psf_mfma) (void)hipFree(sd.psf_mfma);
-  if (sd.obs) (void)hipFree(sd.obs);
-  sd.psf = sd.psf_flip = sd.obs = nullptr;
-  sd.psf_mfma = nullptr;
+  if (sd.owned && sd.base) (void)hipFree(sd.base);
+  sd = SystemData();
 }
 
 int choose_tiles(int P, int HW) {
@@ -183,8 +209,6 @@ static int choose_fwd_tiles(int P, int HW) {
   const int maxt = std::max(1, (HW + kSubThreads - 1) / kSubThreads);
   return std::max(1, std::min(want, maxt));
 }
-
-static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 int beta_per_particle(const ModelCfg& c) { return c.k * c.k * c.H * c.W; }
 

@@ -69,6 +69,50 @@ __global__ void __launch_bounds__(64) logpost_kernel(Group g) {
   s.logpost[p] = isfinite(v) ? v : -INFINITY;
 }
 
+// One 256-lane block per system: the particle with the largest finite log posterior (ties
+// to the lowest index, as fit_result_from_device picks it) and its values, into s.fit_out.
+__global__ void __launch_bounds__(256) fit_best_kernel(Group g) {
+  __shared__ double sv[256];
+  __shared__ int sb[256];
+  const SysDesc& s = g.sys[find_sys(g, blockIdx.x)];
+  const int t = threadIdx.x;
+  double bv = 0.0;
+  int bi = -1;
+  for (int p = t; p < s.P; p += blockDim.x) {  // increasing p: a tie keeps the lower index
+    const double v = s.logpost[p];
+    if (isfinite(v) && (bi < 0 || v > bv)) {
+      bv = v;
+      bi = p;
+    }
+  }
+  sv[t] = bv;
+  sb[t] = bi;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      const int j = sb[t + off];
+      if (j >= 0 && (sb[t] < 0 || sv[t + off] > sv[t] || (sv[t + off] == sv[t] && j < sb[t]))) {
+        sv[t] = sv[t + off];
+        sb[t] = j;
+      }
+    }
+    __syncthreads();
+  }
+  FitOut* o = s.fit_out;
+  const int best = sb[0];
+  if (t == 0) {
+    o->best = best;
+    o->logpost = best >= 0 ? sv[0] : -INFINITY;
+    o->logl = best >= 0 ? s.logl[best] : -INFINITY;
+    o->chi2 = best >= 0 ? s.chi2[best] : INFINITY;
+  }
+  if (best >= 0)
+    for (int j = t; j < s.d; j += blockDim.x) {
+      o->theta[j] = s.theta_out[(size_t)best * s.d + j];
+      o->z[j] = s.z[(size_t)best * s.d + j];
+    }
+}
+
 static int launch_elem(void (*k)(Group), Group& g, int per_sys_threads_fn(const SysDesc&),
                        int threads, hipStream_t st) {
   int b = 0;
@@ -89,6 +133,24 @@ static int n_parts(const SysDesc& s) { return s.P; }
 int launch_fit_init(Group& g, hipStream_t st) { return launch_elem(fit_init_kernel, g, n_elems, 256, st); }
 int launch_adam(Group& g, hipStream_t st) { return launch_elem(adam_kernel, g, n_elems, 256, st); }
 int launch_logpost(Group& g, hipStream_t st) { return launch_elem(logpost_kernel, g, n_parts, 64, st); }
+static int one_block(const SysDesc&) { return 256; }
+int launch_fit_best(Group& g, hipStream_t st) { return launch_elem(fit_best_kernel, g, one_block, 256, st); }
+
+void fit_result_from_out(const FitOut& o, const ModelCfg& c, gl_fit_result* out) {
+  out->d = c.d;
+  out->best = o.best;
+  if (o.best < 0) {
+    out->status = GL_E_NUMERIC;
+    return;
+  }
+  out->status = GL_OK;
+  std::memcpy(out->theta_best, o.theta, sizeof(float) * c.d);
+  std::memcpy(out->z_best, o.z, sizeof(float) * c.d);
+  out->logl_best = o.logl;
+  out->logpost_best = o.logpost;
+  const int dof = c.H * c.W - c.d;
+  out->chi2nu = dof > 0 ? o.chi2 / dof : o.chi2;
+}
 
 // ------------------------------------------------------------------------------------------
 // host helpers
@@ -167,14 +229,14 @@ size_t fit_buffers_bytes(int P, int d) {
          2 * a256(sizeof(double) * P);
 }
 
-int fit_buffers_alloc(FitBuffers& fb, int P, int d, const Prior* host_priors) {
+void fit_buffers_layout(FitBuffers& fb, char* base, int P, int d) {
   fb.P = P;
   fb.d = d;
   fb.bytes = fit_buffers_bytes(P, d);
-  GL_HIP(hipMalloc(&fb.base, fb.bytes));
+  fb.base = base;
   size_t off = 0;
   auto take = [&](size_t b) {
-    char* p = fb.base + off;
+    char* p = base + off;
     off += a256(b);
     return p;
   };
@@ -184,12 +246,19 @@ int fit_buffers_alloc(FitBuffers& fb, int P, int d, const Prior* host_priors) {
   fb.prior = reinterpret_cast<Prior*>(take(sizeof(Prior) * d));
   fb.logpost = reinterpret_cast<double*>(take(sizeof(double) * P));
   fb.chi2 = reinterpret_cast<double*>(take(sizeof(double) * P));
+}
+
+int fit_buffers_alloc(FitBuffers& fb, int P, int d, const Prior* host_priors) {
+  char* base = nullptr;
+  GL_HIP(hipMalloc(&base, fit_buffers_bytes(P, d)));
+  fit_buffers_layout(fb, base, P, d);
+  fb.owned = true;
   GL_HIP(hipMemcpy(fb.prior, host_priors, sizeof(Prior) * d, hipMemcpyHostToDevice));
   return GL_OK;
 }
 
 void fit_buffers_free(FitBuffers& fb) {
-  if (fb.base) (void)hipFree(fb.base);
+  if (fb.owned && fb.base) (void)hipFree(fb.base);
   fb = FitBuffers();
 }
 

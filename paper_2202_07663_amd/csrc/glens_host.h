@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/gl.h"
 #include "glens_types.h"
@@ -72,9 +73,11 @@ void workspace_free(Workspace& ws);
 // Number of sub-pixel work tiles per particle for P particles of an H x W image.
 int choose_tiles(int P, int HW);
 
-// Device copy of the fixed inputs of one system.
+// Device copy of the fixed inputs of one system (one allocation, laid out by system_image).
 struct SystemData {
   ModelCfg cfg;
+  char* base = nullptr;       // the allocation (owned: freed by system_free)
+  bool owned = false;
   float* psf = nullptr;
   float* psf_flip = nullptr;
   uint4* psf_mfma = nullptr;  // Toeplitz fragments of the PSF (K <= kMfmaMaxK), else null
@@ -85,6 +88,12 @@ struct SystemData {
 };
 int system_upload(const gl_model_desc* desc, const ModelCfg& cfg, SystemData& sd);
 void system_free(SystemData& sd);
+// The device image of a system's inputs (PSF, flipped PSF, matrix-core operands, observed
+// image) in host memory, and the binding of SystemData to a device copy of it.
+void system_image(const gl_model_desc* desc, const ModelCfg& cfg, std::vector<uint8_t>& img,
+                  int* psf_mfma_exp);
+void system_bind(SystemData& sd, const ModelCfg& cfg, char* base, size_t img_bytes, int has_obs,
+                 int psf_mfma_exp);
 
 // Fill the launch descriptor of one system.
 SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles);

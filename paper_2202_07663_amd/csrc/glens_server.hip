@@ -1,25 +1,31 @@
 // Continuous-batching fit server: gl_server_create / gl_submit / gl_poll / gl_server_destroy.
 //
 // Requests (one lens system + fit options each) wait in a FIFO queue. A scheduler thread
-// owns one HIP stream and loops over ticks:
-//   1. admit queued requests (FIFO) while an active slot is free and the device memory of
-//      the request (inputs, work space, fit state) fits in the HBM budget;
-//   2. advance every active system by up to steps_per_tick Adam steps; systems with the
-//      same kernel configuration (mass model, shapelet order, PSF size) share one launch
-//      per kernel, so work of systems that arrived at different times overlaps on the GPU;
-//   3. retire systems that reached their step budget: evaluate log L, pick the best
-//      particle, record the result with its timestamps, free its memory.
-// Admission also keeps the active systems' sub-pixel work per step near what fills the GPU
-// (fill_subpixels): large systems then run close to first-come-first-served, which keeps
-// latency low, while small systems are batched into shared launches.
+// owns one HIP stream and keeps the GPU fed with ticks; it never waits on the stream as a
+// whole:
+//   1. admit queued requests (FIFO) while an active slot is free, the device memory of the
+//      request (inputs, work space, fit state) fits in the HBM budget, and the active
+//      systems' sub-pixel work per step stays near what fills the GPU (fill_subpixels).
+//      Admission takes a device block from a pool of blocks released by finished systems
+//      (device memory is allocated only when no cached block fits), writes the system's
+//      inputs into pinned staging memory and enqueues their copy, then the start draws;
+//   2. enqueue a tick: every running system advances by steps_per_tick Adam steps, systems
+//      with the same kernel configuration (mass model, lens light, shapelet order, PSF size)
+//      sharing one launch per kernel, so work of systems that arrived at different times
+//      overlaps on the GPU; systems that reach their step budget then get their log L pass,
+//      the best-particle selection on the device and an asynchronous copy of that result to
+//      pinned host memory; an event marks the end of the tick;
+//   3. reap finished ticks (event queries): their systems' results are recorded with their
+//      timestamps and their blocks and staging go back to the pools. At most two ticks are
+//      in flight: the host prepares tick t + 1 while the GPU runs tick t.
 // A system's arithmetic (work split, summation orders, random starts) depends only on its
-// own request, so its result is the same whether it runs alone or in a mix.
+// own request, so its result is the same whether it runs alone or in a mix, and equal to
+// gl_fit's on the same request.
 #include <hip/hip_runtime.h>
 
 #include <time.h>
 
 #include <algorithm>
-#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -40,6 +46,84 @@ static uint64_t now_ns() {
   return uint64_t(ts.tv_sec) * 1000000000ull + uint64_t(ts.tv_nsec);
 }
 
+static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device blocks cached across systems (scheduler thread only). Sizes are rounded up to
+// sixteenths of the next power of two, so that requests of similar size reuse each other's
+// blocks; a cached block serves a request of up to twice its class.
+class DevicePool {
+ public:
+  static size_t size_class(size_t b) {
+    size_t p = 1;
+    while (p < b) p <<= 1;
+    const size_t step = std::max<size_t>(p / 16, 256);
+    return (b + step - 1) / step * step;
+  }
+  // A block of at least `bytes` (its size in *got), from the cache or hipMalloc.
+  int take(size_t bytes, char** out, size_t* got) {
+    const size_t cls = size_class(bytes);
+    auto it = free_.lower_bound(cls);
+    if (it != free_.end() && it->first <= 2 * cls) {
+      *out = it->second;
+      *got = it->first;
+      cached_ -= it->first;
+      free_.erase(it);
+      return GL_OK;
+    }
+    char* p = nullptr;
+    GL_HIP(hipMalloc(&p, cls));
+    *out = p;
+    *got = cls;
+    return GL_OK;
+  }
+  void give(char* p, size_t bytes) {
+    free_.emplace(bytes, p);
+    cached_ += bytes;
+  }
+  size_t cached() const { return cached_; }
+  // Free cached blocks, largest first, until at most `keep` bytes stay cached.
+  void trim(size_t keep) {
+    while (cached_ > keep && !free_.empty()) {
+      auto it = std::prev(free_.end());
+      (void)hipFree(it->second);
+      cached_ -= it->first;
+      free_.erase(it);
+    }
+  }
+  ~DevicePool() { trim(0); }
+
+ private:
+  std::multimap<size_t, char*> free_;
+  size_t cached_ = 0;
+};
+
+// Pinned host buffers for uploads (scheduler thread only), kept for reuse.
+class PinnedPool {
+ public:
+  int take(size_t bytes, char** out, size_t* got) {
+    const size_t cls = DevicePool::size_class(bytes);
+    auto it = free_.lower_bound(cls);
+    if (it != free_.end() && it->first <= 2 * cls) {
+      *out = it->second;
+      *got = it->first;
+      free_.erase(it);
+      return GL_OK;
+    }
+    void* p = nullptr;
+    GL_HIP(hipHostMalloc(&p, cls, hipHostMallocDefault));
+    *out = static_cast<char*>(p);
+    *got = cls;
+    return GL_OK;
+  }
+  void give(char* p, size_t bytes) { free_.emplace(bytes, p); }
+  ~PinnedPool() {
+    for (auto& kv : free_) (void)hipHostFree(kv.second);
+  }
+
+ private:
+  std::multimap<size_t, char*> free_;
+};
+
 struct Request {
   uint64_t ticket = 0;
   ModelCfg cfg;
@@ -47,31 +131,58 @@ struct Request {
   gl_model_desc desc;  // host pointers re-pointed at psf / obs
   FitParams fp;
   std::vector<Prior> priors;
-  size_t bytes = 0;
+  size_t bytes = 0;   // device block (pool size class)
   double work = 0.0;  // sub-pixel evaluations per step
   uint64_t t_submit = 0;
 };
+
+enum SysState { RUNNING, RETIRING };
 
 struct Active {
   std::unique_ptr<Request> req;
   SystemData sys;
   Workspace ws;
   FitBuffers fb;
+  FitOut* out_dev = nullptr;   // in the block
+  FitOut* out_host = nullptr;  // pinned
+  char* block = nullptr;
+  size_t block_bytes = 0;
   int tiles = 1;
   uint64_t t_admit = 0;
+  SysState state = RUNNING;
+  bool done = false;
   int failed = GL_OK;  // first error of a launch on this system; it then retires with it
 };
 
-static double request_work(const ModelCfg& c, int P) {
-  return double(P) * c.H * c.W * c.k * c.k;
+struct Staged {
+  char* p;
+  size_t bytes;
+};
+
+// One enqueued tick: its end event, the systems whose results it delivers, and the staging
+// buffers whose copies it covers.
+struct Tick {
+  hipEvent_t ev = nullptr;
+  std::vector<Active*> retiring;
+  std::vector<Staged> staging;
+};
+
+static void layout_sizes(const ModelCfg& c, int P, size_t* sys_b, size_t* ws_b, size_t* fb_b) {
+  const int HW = c.H * c.W, KK = c.K * c.K;
+  const size_t tab = c.K <= kMfmaMaxK ? sizeof(uint16_t) * size_t(2) * c.K * 64 * 16 : 0;
+  *sys_b = 2 * al256(sizeof(float) * KK) + al256(tab) + al256(sizeof(float) * HW);
+  *ws_b = workspace_bytes(P, acc_rows_upto(P, HW), HW, c.d, true, beta_per_particle(c));
+  *fb_b = fit_buffers_bytes(P, c.d);
 }
 
 static size_t request_bytes(const ModelCfg& c, int P) {
-  const int HW = c.H * c.W;
-  const size_t psf_tab = c.K <= kMfmaMaxK ? size_t(2) * c.K * 64 * 16 * sizeof(uint16_t) : 0;
-  return sizeof(float) * (2 * c.K * c.K + HW) + psf_tab +
-         workspace_bytes(P, acc_rows_upto(P, HW), HW, c.d, true, beta_per_particle(c)) +
-         fit_buffers_bytes(P, c.d);
+  size_t a, b, f;
+  layout_sizes(c, P, &a, &b, &f);
+  return DevicePool::size_class(a + b + f + al256(sizeof(FitOut)));
+}
+
+static double request_work(const ModelCfg& c, int P) {
+  return double(P) * c.H * c.W * c.k * c.k;
 }
 
 }  // namespace glens
@@ -90,10 +201,17 @@ struct gl_server {
   bool closing = false;
   std::thread th;
   hipStream_t stream = nullptr;
-  // stats (guarded by mu)
-  gl_server_stats st{};
-  std::vector<std::unique_ptr<Active>> active;  // scheduler thread only
-  double active_work = 0.0;                      // scheduler thread only
+  gl_server_stats st{};  // guarded by mu
+  // scheduler thread only
+  std::vector<std::unique_ptr<Active>> active;
+  double active_work = 0.0;  // of the running systems
+  DevicePool pool;
+  PinnedPool pinned;
+  std::deque<Tick> inflight;
+  std::vector<Staged> staged;  // uploads enqueued since the last tick's event
+  std::vector<hipEvent_t> spare_events;
+  FitOut* out_host = nullptr;  // pinned, max_systems slots
+  std::vector<int> free_slots;
 };
 
 static void finish(gl_server* s, Active& a, const gl_fit_result& r) {
@@ -120,47 +238,106 @@ static gl_fit_result error_result(const Active& a, int rc) {
   return r;
 }
 
-static void release(Active& a) {
-  fit_buffers_free(a.fb);
-  workspace_free(a.ws);
-  system_free(a.sys);
+// The system's memory back to the pools (its GPU work is complete, or ordered on the
+// server's stream before any later use of the block).
+static void release(gl_server* s, Active& a) {
+  if (a.block) s->pool.give(a.block, a.block_bytes);
+  a.block = nullptr;
+  if (a.out_host) s->free_slots.push_back(int(a.out_host - s->out_host));
+  a.out_host = nullptr;
+}
+
+static hipEvent_t get_event(gl_server* s) {
+  if (!s->spare_events.empty()) {
+    hipEvent_t e = s->spare_events.back();
+    s->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
 }
 
 static int admit(gl_server* s, std::unique_ptr<Request> rq) {
   auto a = std::make_unique<Active>();
   a->t_admit = now_ns();
-  const ModelCfg& c = rq->cfg;
-  const int HW = c.H * c.W;
-  a->tiles = choose_tiles(rq->fp.P, HW);
-  int rc = system_upload(&rq->desc, c, a->sys);
-  if (!rc) rc = workspace_reserve(a->ws, rq->fp.P, a->tiles, HW, c.d, true, beta_per_particle(c));
-  if (!rc) rc = fit_buffers_alloc(a->fb, rq->fp.P, c.d, rq->priors.data());
   a->req = std::move(rq);
+  const Request& r = *a->req;
+  const ModelCfg& c = r.cfg;
+  const int HW = c.H * c.W, P = r.fp.P;
+  a->tiles = choose_tiles(P, HW);
+  size_t sys_b, ws_b, fb_b;
+  layout_sizes(c, P, &sys_b, &ws_b, &fb_b);
+  // the budget covers the active blocks (this one included) and the cache
+  {
+    size_t in_use;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      in_use = s->st.hbm_in_use;
+    }
+    const size_t room = s->opts.hbm_budget_bytes - std::min(s->opts.hbm_budget_bytes, in_use);
+    if (s->pool.cached() > room) s->pool.trim(room);
+  }
+  int rc = s->pool.take(r.bytes, &a->block, &a->block_bytes);
+  if (!rc && s->free_slots.empty()) rc = set_error(GL_E_DEVICE, "no result slot");
+  if (!rc) {
+    a->out_host = s->out_host + s->free_slots.back();
+    s->free_slots.pop_back();
+    std::vector<uint8_t> img;
+    int sx = 0;
+    system_image(&r.desc, c, img, &sx);
+    system_bind(a->sys, c, a->block, img.size(), 1, sx);
+    workspace_layout(a->ws, a->block + sys_b, P, acc_rows_upto(P, HW), HW, c.d, true,
+                     beta_per_particle(c));
+    fit_buffers_layout(a->fb, a->block + sys_b + ws_b, P, c.d);
+    a->out_dev = reinterpret_cast<FitOut*>(a->block + sys_b + ws_b + fb_b);
+    const size_t pri_b = sizeof(Prior) * c.d;
+    Staged stg{nullptr, 0};
+    rc = s->pinned.take(img.size() + pri_b, &stg.p, &stg.bytes);
+    if (!rc) {
+      std::memcpy(stg.p, img.data(), img.size());
+      std::memcpy(stg.p + img.size(), r.priors.data(), pri_b);
+      const hipError_t e1 =
+          hipMemcpyAsync(a->block, stg.p, img.size(), hipMemcpyHostToDevice, s->stream);
+      const hipError_t e2 = hipMemcpyAsync(a->fb.prior, stg.p + img.size(), pri_b,
+                                           hipMemcpyHostToDevice, s->stream);
+      s->staged.push_back(stg);  // given back when the next tick's event completes
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        rc = set_error(GL_E_DEVICE, "input upload failed");
+      }
+    }
+  }
   if (!rc) {
     Group g;
     std::memset(&g, 0, sizeof(g));
     g.nsys = 1;
-    g.sys[0] = make_sys(a->sys, a->ws, a->req->fp.P, a->tiles);
+    g.sys[0] = make_sys(a->sys, a->ws, P, a->tiles);
     attach_fit(g.sys[0], a->fb, a->req->fp, a->ws);
     rc = launch_fit_init(g, s->stream);
   }
-  if (rc) {  // retired at once with the error; the stream has no work of it in flight
-    s->active_work -= a->req->work;
-    if (hipStreamSynchronize(s->stream) != hipSuccess) rc = GL_E_DEVICE;
-    const gl_fit_result r = error_result(*a, rc);
-    release(*a);
-    finish(s, *a, r);
+  if (rc) {
+    // nothing of it runs later; copies already enqueued into its block are ordered on the
+    // stream before any reuse of the block
+    const gl_fit_result res = error_result(*a, rc);
+    release(s, *a);
+    finish(s, *a, res);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.active = int(s->active.size());
     return rc;
   }
+  s->active_work += r.work;
   s->active.push_back(std::move(a));
   return GL_OK;
 }
 
-// Systems grouped by kernel configuration; each group runs `mode` and, for mode 2, Adam. A
-// group whose launches fail marks its systems (they retire with the error at the end of the
-// tick); the other groups go on.
-static int run_grouped(gl_server* s, std::vector<Active*>& sys, int mode) {
-  int first_rc = GL_OK;
+// Systems grouped by kernel configuration; each group runs `mode` (2: one Adam step; 1: the
+// log L pass, the log posterior and the best-particle selection). A group whose launches
+// fail marks its systems (they retire with the error); the other groups go on.
+static void run_grouped(gl_server* s, const std::vector<Active*>& sys, int mode) {
   std::map<std::pair<int, int>, std::vector<Active*>> by_key;
   for (Active* a : sys) by_key[{subpix_key(a->req->cfg), a->req->cfg.K}].push_back(a);
   for (auto& kv : by_key) {
@@ -173,97 +350,158 @@ static int run_grouped(gl_server* s, std::vector<Active*>& sys, int mode) {
         Active* a = list[i0 + i];
         g.sys[i] = make_sys(a->sys, a->ws, a->req->fp.P, a->tiles);
         attach_fit(g.sys[i], a->fb, a->req->fp, a->ws);
+        g.sys[i].fit_out = a->out_dev;
       }
       int rc = run_group(g, kv.first.first, kv.first.second, mode, s->stream);
       if (!rc && mode == 2) rc = launch_adam(g, s->stream);
       if (!rc && mode == 1) rc = launch_logpost(g, s->stream);
-      if (rc) {
+      if (!rc && mode == 1) rc = launch_fit_best(g, s->stream);
+      if (rc)
         for (int i = 0; i < g.nsys; ++i)
           if (list[i0 + i]->failed == GL_OK) list[i0 + i]->failed = rc;
-        if (first_rc == GL_OK) first_rc = rc;
-      }
     }
   }
-  return first_rc;
 }
 
-static void tick(gl_server* s) {
-  // 1. admission
-  while (true) {
-    std::unique_ptr<Request> rq;
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      if (s->queue.empty() || int(s->active.size()) >= s->opts.max_systems) break;
-      if (s->st.hbm_in_use + s->queue.front()->bytes > s->opts.hbm_budget_bytes) break;
-      if (!s->active.empty() && s->active_work + s->queue.front()->work > s->opts.fill_subpixels)
-        break;
-      rq = std::move(s->queue.front());
-      s->queue.pop_front();
-      s->st.hbm_in_use += rq->bytes;
-      s->st.hbm_peak = std::max(s->st.hbm_peak, s->st.hbm_in_use);
-      s->st.admitted++;
-      s->st.queued = int(s->queue.size());
+// Retire the systems of the oldest in-flight tick once it has completed (wait: block on it).
+static bool reap_one(gl_server* s, bool wait) {
+  if (s->inflight.empty()) return false;
+  Tick& t = s->inflight.front();
+  const hipError_t e = wait ? hipEventSynchronize(t.ev) : hipEventQuery(t.ev);
+  if (e == hipErrorNotReady) return false;
+  const bool device_ok = e == hipSuccess;
+  if (!device_ok) (void)hipGetLastError();
+  for (Active* a : t.retiring) {
+    gl_fit_result r;
+    if (a->failed != GL_OK || !device_ok) {
+      r = error_result(*a, a->failed != GL_OK ? a->failed : GL_E_DEVICE);
+    } else {
+      std::memset(&r, 0, sizeof(r));
+      fit_result_from_out(*a->out_host, a->req->cfg, &r);
+      r.t_submit = a->req->t_submit;
+      r.t_admit = a->t_admit;
+      r.t_done = now_ns();
     }
-    s->active_work += rq->work;
-    admit(s, std::move(rq));  // a failure retires the request with its status
+    release(s, *a);
+    finish(s, *a, r);
+    a->done = true;
   }
-  if (s->active.empty()) return;
-  // 2. advance every active system by up to steps_per_tick steps
+  for (const Staged& st : t.staging) s->pinned.give(st.p, st.bytes);
+  s->spare_events.push_back(t.ev);
+  s->inflight.pop_front();
+  s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                 [](const std::unique_ptr<Active>& a) { return a->done; }),
+                  s->active.end());
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->st.active = int(s->active.size());
+  return true;
+}
+
+// Enqueue one tick of the running systems, then its end event.
+static void enqueue_tick(gl_server* s) {
+  std::vector<Active*> running;
+  for (auto& a : s->active)
+    if (a->state == RUNNING) running.push_back(a.get());
   for (int k = 0; k < s->opts.steps_per_tick; ++k) {
     std::vector<Active*> run;
-    for (auto& a : s->active)
-      if (a->failed == GL_OK && a->req->fp.step < a->req->fp.K) run.push_back(a.get());
+    for (Active* a : running)
+      if (a->failed == GL_OK && a->req->fp.step < a->req->fp.K) run.push_back(a);
     if (run.empty()) break;
     run_grouped(s, run, 2);
     for (Active* a : run)
       if (a->failed == GL_OK) a->req->fp.step++;
   }
-  // 3. retire finished and failed systems
-  auto done = [](const Active& a) { return a.failed != GL_OK || a.req->fp.step >= a.req->fp.K; };
+  Tick t;
   std::vector<Active*> fin;
-  for (auto& a : s->active)
-    if (a->failed == GL_OK && a->req->fp.step >= a->req->fp.K) fin.push_back(a.get());
-  if (!fin.empty()) run_grouped(s, fin, 1);
-  if (hipStreamSynchronize(s->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    for (auto& a : s->active)
-      if (a->failed == GL_OK) a->failed = GL_E_DEVICE;
-  }
-  for (auto& ap : s->active) {
-    Active* a = ap.get();
-    if (!done(*a)) continue;
+  for (Active* a : running) {
+    if (a->failed == GL_OK && a->req->fp.step < a->req->fp.K) continue;
+    if (a->failed == GL_OK) fin.push_back(a);
+    a->state = RETIRING;
     s->active_work -= a->req->work;
-    gl_fit_result r;
-    if (a->failed != GL_OK) {
-      r = error_result(*a, a->failed);
-    } else {
-      std::memset(&r, 0, sizeof(r));
-      int rc = fit_result_from_device(a->fb, a->ws, a->req->fp.P, a->req->cfg, s->stream, &r);
-      if (rc) r.status = rc;
-      r.t_submit = a->req->t_submit;
-      r.t_admit = a->t_admit;
-      r.t_done = now_ns();
-    }
-    release(*a);
-    finish(s, *a, r);
+    t.retiring.push_back(a);
   }
-  s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
-                                 [&](const std::unique_ptr<Active>& a) { return done(*a); }),
-                  s->active.end());
-  std::lock_guard<std::mutex> lk(s->mu);
-  s->st.ticks++;
-  s->st.active = int(s->active.size());
+  if (!fin.empty()) run_grouped(s, fin, 1);
+  for (Active* a : fin)
+    if (a->failed == GL_OK &&
+        hipMemcpyAsync(a->out_host, a->out_dev, sizeof(FitOut), hipMemcpyDeviceToHost,
+                       s->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      a->failed = GL_E_DEVICE;
+    }
+  t.staging.swap(s->staged);
+  t.ev = get_event(s);
+  if (!t.ev || hipEventRecord(t.ev, s->stream) != hipSuccess) {
+    // no event to track this tick: finish it here, and mark it with a fresh event if one can
+    // be made (otherwise its systems retire with a device error)
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s->stream);
+    if (!t.ev) t.ev = get_event(s);
+    if (!t.ev || hipEventRecord(t.ev, s->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      for (Active* a : t.retiring)
+        if (a->failed == GL_OK) a->failed = GL_E_DEVICE;
+      if (!t.ev) {  // retire without an event
+        for (Active* a : t.retiring) {
+          const gl_fit_result r = error_result(*a, a->failed);
+          release(s, *a);
+          finish(s, *a, r);
+          a->done = true;
+        }
+        for (const Staged& st : t.staging) s->pinned.give(st.p, st.bytes);
+        return;
+      }
+    }
+  }
+  s->inflight.push_back(std::move(t));
 }
 
 static void scheduler(gl_server* s) {
   (void)hipSetDevice(s->device);
   while (true) {
+    while (reap_one(s, false)) {
+    }
+    s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                   [](const std::unique_ptr<Active>& a) { return a->done; }),
+                    s->active.end());
+    bool have_queue;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv.wait(lk, [&] { return s->closing || !s->queue.empty() || !s->active.empty(); });
-      if (s->closing && s->queue.empty() && s->active.empty()) break;
+      if (s->closing && s->queue.empty() && s->active.empty() && s->inflight.empty()) break;
+      if (s->queue.empty() && s->active.empty() && s->inflight.empty()) {
+        s->cv.wait(lk, [&] { return s->closing || !s->queue.empty(); });
+        continue;
+      }
+      have_queue = !s->queue.empty();
     }
-    tick(s);
+    // admission (FIFO) under the slot, budget and fill limits
+    while (have_queue) {
+      std::unique_ptr<Request> rq;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->queue.empty() || int(s->active.size()) >= s->opts.max_systems) break;
+        if (s->st.hbm_in_use + s->queue.front()->bytes > s->opts.hbm_budget_bytes) break;
+        if (s->active_work > 0.0 &&
+            s->active_work + s->queue.front()->work > s->opts.fill_subpixels)
+          break;
+        rq = std::move(s->queue.front());
+        s->queue.pop_front();
+        s->st.hbm_in_use += rq->bytes;
+        s->st.hbm_peak = std::max(s->st.hbm_peak, s->st.hbm_in_use);
+        s->st.admitted++;
+        s->st.queued = int(s->queue.size());
+      }
+      admit(s, std::move(rq));  // a failure retires the request with its status
+    }
+    bool any_running = false;
+    for (auto& a : s->active) any_running = any_running || a->state == RUNNING;
+    if (any_running) {
+      enqueue_tick(s);
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->st.ticks++;
+      s->st.active = int(s->active.size());
+    }
+    // at most two ticks in flight; with nothing to enqueue, wait for the oldest
+    if (s->inflight.size() >= 2 || (!any_running && !s->inflight.empty())) reap_one(s, true);
   }
 }
 
@@ -281,10 +519,18 @@ int gl_server_create(const gl_server_opts* o, gl_server** out) {
   if (!s) return set_error(GL_E_NOMEM, "host allocation failed");
   s->opts = *o;
   if (!(s->opts.fill_subpixels > 0.0)) s->opts.fill_subpixels = 6e7;
-  if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
+  void* slots = nullptr;
+  if (hipGetDevice(&s->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc(&slots, sizeof(FitOut) * size_t(o->max_systems), hipHostMallocDefault) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
-    return set_error(GL_E_DEVICE, "cannot create the server stream");
+    return set_error(GL_E_DEVICE, "cannot create the server stream or result slots");
   }
+  s->out_host = static_cast<FitOut*>(slots);
+  for (int i = o->max_systems - 1; i >= 0; --i) s->free_slots.push_back(i);
   s->th = std::thread(scheduler, s);
   *out = s;
   return GL_OK;
@@ -299,8 +545,12 @@ int gl_server_destroy(gl_server* s) {
   }
   s->cv.notify_all();
   s->th.join();
+  (void)hipStreamSynchronize(s->stream);
+  for (const Staged& st : s->staged) s->pinned.give(st.p, st.bytes);
+  for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
+  (void)hipHostFree(s->out_host);
   (void)hipStreamDestroy(s->stream);
-  delete s;
+  delete s;  // the pools free their blocks
   return GL_OK;
 }
 
