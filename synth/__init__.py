@@ -297,7 +297,7 @@ def add_noise(clean: np.ndarray, seed: int, sigma_bkg: float, t_exp: float,
 # paper's broadened prior (blue entries of eq. sim-dist) where its parameter and scale
 # match these workloads; lens-light radius, source radius and source intensity are centred
 # on these workloads' draws instead. Shapelets (no prior in the paper): beta uniform on
-# (0.02, 0.4), coefficients N(0, 10).
+# (0.02, 0.4), coefficients N(0, 2) (the draws' N(0, 1) broadened by the paper's factor 2).
 # ----------------------------------------------------------------------------------------
 NORMAL, LOGNORMAL, TRUNCNORMAL, UNIFORM = 0, 1, 2, 3
 
@@ -333,6 +333,8 @@ def fit_priors(spec: Spec) -> list:
     pr += [LN(0.25, 0.5), U(0.5, 8.0), TN(0, 0.3, -0.5, 0.5), TN(0, 0.3, -0.5, 0.5),
            N(0, 0.5), N(0, 0.5), LN(12.0, 0.9)]
     if spec.nmax >= 0:
-        pr += [U(0.02, 0.4)] + [N(0, 10.0)] * n_shapelet_coeffs(spec.nmax)
+        # shapelets: beta over (0.02, 0.4) (draws U[0.05, 0.2]); coefficients N(0, 2), the
+        # draws' N(0, 1) broadened x2 as every normal prior of eq. sim-dist is
+        pr += [U(0.02, 0.4)] + [N(0, 2.0)] * n_shapelet_coeffs(spec.nmax)
     assert len(pr) == spec.d
     return [dict(p) for p in pr]
