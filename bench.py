@@ -271,21 +271,23 @@ def cpu_baseline(spec, obs, theta, n_sample: int, n_one: int = 8):
 # observed images come from gl_simulate of a seeded truth plus seeded noise.
 # ------------------------------------------------------------------------------------------
 
-def make_stream(n, seed, G, small=False):
-    """n requests of the mixed stream (sizes {40, 60, 80, 100} px, P a multiple of 256 in
-    [512, 4096]), or with small=True of systems that each underfill the GPU (sizes {40, 48,
-    56, 60} px, P in {512, 768, 1024}); component sets mixed in both."""
+def make_stream(n, seed, G, small=False, tiny=False):
+    """n requests of the mixed stream (sizes {40, 60, 80, 100} px, k = 2, P a multiple of 256
+    in [512, 4096]); with small=True of the smaller systems of that range (sizes {40, 48, 56,
+    60} px, P in {512, 768, 1024}); with tiny=True of systems whose launches alone leave most
+    of the GPU idle (sizes {32, 40} px, k = 1, P in {64, 128, 256}). Component sets mixed."""
     import synth
     import torch
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
-        N = int(rng.choice([40, 48, 56, 60] if small else [40, 60, 80, 100]))
+        N = int(rng.choice([32, 40] if tiny else ([40, 48, 56, 60] if small else [40, 60, 80, 100])))
         epl = bool(rng.integers(2))
         ll = bool(rng.integers(2))
         nmax = int(rng.choice([-1, 4, 6, 8]))
-        P = int(256 * (rng.integers(2, 5) if small else rng.integers(2, 17)))
-        spec = synth.spec_custom(N, 2, epl, ll, nmax, K=21)
+        P = int(rng.choice([64, 128, 256])) if tiny else \
+            int(256 * (rng.integers(2, 5) if small else rng.integers(2, 17)))
+        spec = synth.spec_custom(N, 1 if tiny else 2, epl, ll, nmax, K=21)
         truth = synth.draw_truth(spec, 1000 + i)
         m = G.Model.from_spec(spec, None)
         clean = m.simulate(torch.from_numpy(truth[None, :]).cuda()).cpu().numpy()[0]
@@ -364,12 +366,36 @@ def serial_stream(G, stream, K, arrivals):
     return makespan, lat, [res[i] for i in range(len(stream))]
 
 
-def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small=False):
+def serving_poisson_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16,
+                          pilot=50):
+    """A long stream at stable load: the plain loop's service rate from its first `pilot`
+    systems, then both the server and the plain loop under the same Poisson arrivals at 0.8 x
+    that rate (no burst runs)."""
+    import paper_2202_07663_amd as G
+    stream = make_stream(n_systems, seed, G)
+    pil_span, _, _ = serial_stream(G, stream[:pilot], K, np.zeros(pilot))
+    lam = 0.8 * pilot / pil_span
+    arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / lam, len(stream)))
+    span, lat, _, st = serve_stream(G, stream, K, arr, steps_per_tick, max_systems)
+    ser_span, ser_lat, _ = serial_stream(G, stream, K, arr)
+    q = lambda x, p: round(float(np.percentile(x, p)), 4)  # noqa: E731
+    return {"stream": "mixed (40-100 px, P 512-4096), Poisson arrivals", "systems": len(stream),
+            "K": K, "poisson_rate_per_s": round(lam, 4), "pilot_systems": pilot,
+            "makespan_s_served": round(span, 2), "makespan_s_serial": round(ser_span, 2),
+            "fits_per_hour_served": round(3600 * len(stream) / span, 1),
+            "fits_per_hour_serial": round(3600 * len(stream) / ser_span, 1),
+            "p50_latency_s": q(lat, 50), "p99_latency_s": q(lat, 99),
+            "p50_latency_serial_s": q(ser_lat, 50), "p99_latency_serial_s": q(ser_lat, 99),
+            "hbm_peak_bytes": int(st["hbm_peak"])}
+
+
+def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small=False,
+                  tiny=False):
     """Served against the plain loop on the same requests: a burst (all at t = 0: throughput)
     and Poisson arrivals at 0.8 x the plain loop's service rate (latency at stable load), each
     run for real by both; the plain loop's rate is taken from its own burst run."""
     import paper_2202_07663_amd as G
-    stream = make_stream(n_systems, seed, G, small)
+    stream = make_stream(n_systems, seed, G, small, tiny)
     burst = np.zeros(len(stream))
     ser_span, ser_lat_b, ser_res = serial_stream(G, stream, K, burst)
     span, lat_b, res_b, st_b = serve_stream(G, stream, K, burst, steps_per_tick, max_systems)
@@ -383,7 +409,8 @@ def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small
     q = lambda x, p: round(float(np.percentile(x, p)), 4)  # noqa: E731
     sub = sum(sp.H * sp.W * sp.k ** 2 * P for sp, _, P, _ in stream) / len(stream)
     return {
-        "stream": "small (40-60 px, P 512-1024)" if small else "mixed (40-100 px, P 512-4096)",
+        "stream": ("tiny (32-40 px, k 1, P 64-256)" if tiny else
+                   "small (40-60 px, P 512-1024)" if small else "mixed (40-100 px, P 512-4096)"),
         "systems": len(stream), "K": K, "steps_per_tick": steps_per_tick,
         "max_systems": max_systems, "mean_subpixels_per_step": round(sub),
         "fits_per_hour_served": round(3600 * len(stream) / span, 1),
@@ -423,6 +450,9 @@ def main():
     ap.add_argument("--serve-systems", type=int, default=32,
                     help="systems in the serving stream (0 skips the serving measurement)")
     ap.add_argument("--serve-steps", type=int, default=300, help="Adam steps per fit")
+    ap.add_argument("--serve-poisson-only", action="store_true",
+                    help="run only the long serving stream under Poisson arrivals "
+                         "(--serve-systems requests; e.g. 500) and print its JSON line")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the MAP -> VI -> HMC pipeline measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -444,6 +474,11 @@ def main():
 
     import torch
     import paper_2202_07663_amd as G
+
+    if args.serve_poisson_only:
+        r = serving_poisson_bench(args.serve_systems, args.serve_steps)
+        print(json.dumps(_finite({"serving_poisson": r}), allow_nan=False), flush=True)
+        return
 
     spec, obs, theta_np = workload()
     P = theta_np.shape[0]
@@ -543,6 +578,7 @@ def main():
     if args.serve_systems > 0:
         out["serving"] = serving_bench(args.serve_systems, args.serve_steps)
         out["serving_small"] = serving_bench(args.serve_systems, args.serve_steps, small=True)
+        out["serving_tiny"] = serving_bench(args.serve_systems, args.serve_steps, tiny=True)
     if not args.no_pipeline:
         import synth
         # the whole fit of the 60x60 EPL + shapelet system: 4096 starts, VI 1000 x 1000, HMC

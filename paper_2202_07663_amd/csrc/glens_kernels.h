@@ -432,13 +432,18 @@ __device__ __forceinline__ void mfma_tiles(const uint16_t* x, int nel, const Mfm
   }
 }
 
-// Per-pixel state of the matrix-core PSF kernel.
+// Per-pixel state of the matrix-core PSF kernel. The launch descriptor's fields are copied
+// here once: read through the descriptor (a dynamically indexed kernel argument) they were
+// loaded again for every pixel.
 struct MfmaPass {
-  const SysDesc& s;
   const MfmaGeom& q;
-  int part, wave;
-  int unscale;  // exponent that takes the scaled sums back: -(image scale + PSF scale)
-  float* seed;  // LDS [H][W]
+  int wave;
+  int unscale;        // exponent that takes the scaled sums back: -(image scale + PSF scale)
+  int H, W, mode;
+  float s2b, inv_gt, inv_k2;
+  const float* obs;   // [H][W]
+  float* out;         // this particle's model image (mode 0) or sbar (adjoint pass)
+  float* seed;        // LDS [H][W]
   double ll, c2;
 };
 
@@ -446,33 +451,33 @@ struct MfmaPass {
 // Forward (ADJ false): the model image, or the likelihood terms and the seed; adjoint: sbar.
 template <int U0, int G, bool ADJ>
 __device__ __forceinline__ void mfma_pixels(MfmaPass& P, const f32x4* acc) {
-  const SysDesc& s = P.s;
   const int lane = threadIdx.x & 63, n = lane & 15, r0 = 4 * (lane >> 4);
-  const int H = s.H, W = s.W, HW = H * W;
+  const int H = P.H, W = P.W;
 #pragma unroll
   for (int v = 0; v < G; ++v) {
     const int t = P.wave + 4 * (U0 + v), tr = t / P.q.TC, tc = t - tr * P.q.TC;
     const int j = tc * P.q.N + n, i0 = tr * 16 + r0;
+    if (n >= P.q.N || j >= W) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + r;
-      if (n >= P.q.N || j >= W || i >= H) continue;
+      if (i >= H) break;
       const float m = ldexpf(acc[v][r], P.unscale);
-      const size_t px = (size_t)P.part * HW + i * W + j;
+      const int px = i * W + j;
       if (ADJ) {
-        s.sbar[px] = m * s.inv_k2;
-      } else if (s.mode == 0) {
-        s.img[px] = m;
+        P.out[px] = m * P.inv_k2;
+      } else if (P.mode == 0) {
+        P.out[px] = m;
       } else {
         const float pos = m > 0.f ? m : 0.f;
-        const float s2 = s.s2b + pos * s.inv_gt;
-        const float res = s.obs[i * W + j] - m;
+        const float s2 = P.s2b + pos * P.inv_gt;
+        const float res = P.obs[px] - m;
         const float is2 = rcp_f32(s2);
         const float chi = res * res * is2;
         P.c2 += double(chi);
         P.ll += double(chi + kLn2f * log2_f32(6.283185307179586f * s2));
-        const float sp = m > 0.f ? s.inv_gt : 0.f;
-        P.seed[i * W + j] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
+        const float sp = m > 0.f ? P.inv_gt : 0.f;
+        P.seed[px] = res * is2 + 0.5f * sp * (res * res * is2 * is2 - is2);
       }
     }
   }
@@ -481,9 +486,9 @@ __device__ __forceinline__ void mfma_pixels(MfmaPass& P, const f32x4* acc) {
 // Tiles U0 .. U0 + G - 1 of the wave: correlate, then the per-pixel step.
 template <int U0, int G, bool ADJ>
 __device__ __forceinline__ void mfma_group(MfmaPass& P, const uint16_t* x, int nel,
-                                           const uint4* tab) {
+                                           const uint4* tab, int K) {
   f32x4 acc[G];
-  mfma_tiles<U0, G>(x, nel, P.q, tab, P.s.K, P.wave, acc);
+  mfma_tiles<U0, G>(x, nel, P.q, tab, K, P.wave, acc);
   mfma_pixels<U0, G, ADJ>(P, acc);
 }
 
@@ -491,9 +496,9 @@ __device__ __forceinline__ void mfma_group(MfmaPass& P, const uint16_t* x, int n
 // group's products hide the latency of the PSF fragment loads only when it has several tiles.
 template <bool ADJ>
 __device__ __forceinline__ void mfma_pass(MfmaPass& P, const uint16_t* x, int nel,
-                                          const uint4* tab, int ntw) {
+                                          const uint4* tab, int K, int ntw) {
   static_assert(kMfmaWaveTiles == 16, "group table for up to 16 tiles");
-#define GL_G(U0, G) mfma_group<U0, G, ADJ>(P, x, nel, tab)
+#define GL_G(U0, G) mfma_group<U0, G, ADJ>(P, x, nel, tab, K)
   switch (ntw) {
     case 1: GL_G(0, 1); break;
     case 2: GL_G(0, 2); break;
@@ -552,8 +557,9 @@ conv_mfma_kernel(Group g) {
   const int wave = threadIdx.x >> 6;
   // tiles of this wave (wave-uniform: kept in a scalar register)
   const int ntw = __builtin_amdgcn_readfirstlane(wave < q.T ? (q.T - wave + 3) / 4 : 0);
-  MfmaPass P{s, q, part, wave, -(sx + s.psf_mfma_exp), seed, 0.0, 0.0};
-  mfma_pass<false>(P, xlds, nel, s.psf_mfma, ntw);
+  MfmaPass P{q, wave, -(sx + s.psf_mfma_exp), H, W, mode, s.s2b, s.inv_gt, s.inv_k2, s.obs,
+             (mode == 0 ? s.img : s.sbar) + (size_t)part * HW, seed, 0.0, 0.0};
+  mfma_pass<false>(P, xlds, nel, s.psf_mfma, K, ntw);
   if (mode == 0) return;
   const double tot = block_sum(P.ll, red);
   if (threadIdx.x == 0) {
@@ -577,7 +583,8 @@ conv_mfma_kernel(Group g) {
   __syncthreads();
   // d logL / d m0 = correlation of the pixel seed with the (unflipped) PSF
   P.unscale = -(ss + s.psf_mfma_exp);
-  mfma_pass<true>(P, xlds, nel, s.psf_mfma + 2 * 64 * K, ntw);
+  P.out = s.sbar + (size_t)part * HW;
+  mfma_pass<true>(P, xlds, nel, s.psf_mfma + 2 * 64 * K, K, ntw);
 }
 
 // ------------------------------------------------------------------------------------------
