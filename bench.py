@@ -323,11 +323,19 @@ def _replay(stream, arrivals, start, done):
             if wait > 0:
                 time.sleep(wait)
             start(i)
+            _progress("submitted", i + 1, len(stream))
 
     th = threading.Thread(target=submitter)
     th.start()
     res = done(th)
     return time.perf_counter() - t0, res
+
+
+def _progress(what, i, n):
+    """A line on stderr every 50 systems of a long stream (the JSON line stays alone on
+    stdout)."""
+    if n >= 100 and (i % 50 == 0 or i == n):
+        print(f"{what} {i}/{n} at {time.strftime('%H:%M:%S')}", file=sys.stderr, flush=True)
 
 
 def serve_stream(G, stream, K, arrivals, steps_per_tick, max_systems):
@@ -342,7 +350,11 @@ def serve_stream(G, stream, K, arrivals, steps_per_tick, max_systems):
 
     def done(th):
         th.join()
-        return [srv.wait(t) for t in tickets]
+        out = []
+        for i, t in enumerate(tickets):
+            out.append(srv.wait(t))
+            _progress("served", i + 1, len(tickets))
+        return out
 
     makespan, res = _replay(stream, arrivals, start, done)
     st = srv.stats()
@@ -371,6 +383,7 @@ def serial_stream(G, stream, K, arrivals):
             res[i] = G.fit(m, P, K, pri, seed=7)
             m.close()
             t_done[i] = time.perf_counter()
+            _progress("serial", len(t_done), len(stream))
         th.join()
         return None
 
@@ -440,6 +453,118 @@ def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small
     }
 
 
+def c4_bench(G, spec):
+    """The whole fit of the 60x60 EPL + shapelet system (stored observation, seed 0): 4096
+    starts, VI 1000 x 1000, HMC 64 chains x (250 + 750) trajectories x 10 leapfrog steps; then
+    the same MAP point with a longer surrogate fit and longer chains."""
+    import torch
+    import synth
+    # At this signal-to-noise (sigma_bkg 0.1, t_exp 1000 s) and d = 51 the multi-start Adam
+    # needs ~1e4 steps to reach the global mode; Table 1's 300 steps are run and reported
+    # beside it.
+    obs0, truth0 = stored(spec, 0)
+    m0 = G.Model.from_spec(spec, obs0)
+    t0 = time.perf_counter()
+    r300 = G.fit(m0, 4096, 300, synth.fit_priors(spec), seed=0)
+    torch.cuda.synchronize()
+    map300 = {"K": 300, "P": 4096, "chi2nu": round(r300["chi2nu"], 4),
+              "seconds": round(time.perf_counter() - t0, 3)}
+    print("c4: MAP at 300 steps done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r_map = G.fit(m0, 4096, 10000, synth.fit_priors(spec), seed=0)
+    torch.cuda.synchronize()
+    map_res = (r_map, time.perf_counter() - t0)
+    m0.close()
+    print("c4: MAP at 10000 steps done", file=sys.stderr, flush=True)
+    out = {}
+    out["c4_pipeline"] = dict(workload="epl60_s0", map_at_table1_budget=map300,
+                              **pipeline_bench(spec, obs0, truth0, n_map=4096, k_map=10000,
+                                               n_vi=1000, k_vi=1000, chains=64, L=10,
+                                               n_burn=250, n_samples=750,
+                                               adapt_length=False, map_result=map_res))
+    print("c4: Table 1 VI and HMC done", file=sys.stderr, flush=True)
+    # the same MAP point with a longer surrogate fit (Table 1's 1000 iterations at 1e-3
+    # cannot shrink the surrogate from sd 1e-3 to this posterior's widths of 1e-4 and
+    # below) and longer chains
+    out["c4_pipeline_long"] = dict(workload="epl60_s0", **pipeline_bench(
+        spec, obs0, truth0, n_map=4096, k_map=10000, n_vi=1000, k_vi=6000, chains=64, L=10,
+        n_burn=1000, n_samples=1000, adapt_length=False, vi_lr=3e-3, vi_warmup=300,
+        map_result=map_res))
+    return out
+
+
+def trace_summary(path, gap_split_s=0.1, min_dispatches=200):
+    """Phases of a rocprofv3 kernel trace (the `*_kernel_trace.csv` of `--kernel-trace`), as
+    markdown. A phase is a maximal run of this library's dispatches from one host thread with
+    one driver family (fit: fit_/adam_/logpost_ kernels; vi_; hmc_; the likelihood kernels
+    belong to the family around them) and no idle gap above gap_split_s. Per phase: span,
+    busy (the union of all kernels' execution intervals in the span, over the span), the gaps
+    between consecutive kernels, and the kernels taking the most time."""
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"],
+                         r["Thread_Id"]))
+    rows.sort()
+
+    def short(name):
+        if "glens::" not in name:
+            return None
+        return name.split("glens::", 1)[1].split("(")[0].split("<")[0]
+
+    def family(k):
+        for pre, fam in (("hmc_", "hmc"), ("vi_", "vi"), ("fit_", "fit"), ("adam_", "fit"),
+                         ("logpost_", "fit")):
+            if k.startswith(pre):
+                return fam
+        return None
+
+    phases, cur = [], None
+    for t0, t1, name, tid in rows:
+        k = short(name)
+        if k is None:
+            if cur is not None:
+                cur["all"].append((t0, t1))
+            continue
+        fam = family(k)
+        brk = (cur is None or tid != cur["tid"] or (fam is not None and cur["fam"] is not None
+                                                   and fam != cur["fam"])
+               or t0 - cur["end"] > gap_split_s * 1e9)
+        if brk:
+            cur = {"tid": tid, "fam": fam, "own": [], "all": [], "end": t1}
+            phases.append(cur)
+        if cur["fam"] is None:
+            cur["fam"] = fam
+        cur["own"].append((t0, t1, k))
+        cur["all"].append((t0, t1))
+        cur["end"] = max(cur["end"], t1)
+    lines = ["| phase | host thread | family | dispatches | span s | busy | gap p50 us | "
+             "gap p90 us | kernels (calls, avg us) |", "|---" * 9 + "|"]
+    for n, ph in enumerate(phases):
+        own = ph["own"]
+        if len(own) < min_dispatches:
+            continue
+        a, b = own[0][0], max(t1 for _, t1, _ in own)
+        iv = sorted((max(t0, a), min(t1, b)) for t0, t1 in ph["all"] if t1 > a and t0 < b)
+        busy, hi = 0, a
+        for t0, t1 in iv:
+            if t1 > hi:
+                busy += t1 - max(t0, hi)
+                hi = t1
+        gaps = np.array([max(0, own[i + 1][0] - own[i][1]) for i in range(len(own) - 1)]) * 1e-3
+        tot = {}
+        for t0, t1, k in own:
+            c, d = tot.get(k, (0, 0))
+            tot[k] = (c + 1, d + t1 - t0)
+        top = sorted(tot.items(), key=lambda kv: -kv[1][1])[:7]
+        ks = ", ".join(f"{k} ({c}, {d / c * 1e-3:.1f})" for k, (c, d) in top)
+        lines.append(f"| {n} | {ph['tid']} | {ph['fam'] or 'lens'} | {len(own)} | "
+                     f"{(b - a) * 1e-9:.3f} | {busy / max(b - a, 1):.3f} | "
+                     f"{np.percentile(gaps, 50):.1f} | {np.percentile(gaps, 90):.1f} | {ks} |")
+    return "\n".join(lines)
+
+
 def _finite(x):
     """JSON has no inf / nan: non-finite numbers are written as null."""
     if isinstance(x, dict):
@@ -469,9 +594,19 @@ def main():
                          "(--serve-systems requests; e.g. 500) and print its JSON line")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the MAP -> VI -> HMC pipeline measurement")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="run only the whole fit of the 60x60 EPL + shapelet system (MAP, VI, "
+                         "HMC) and print its JSON")
+    ap.add_argument("--serve-only", choices=["mixed", "small", "tiny"],
+                    help="run only the served-against-plain-loop measurement of one stream")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print the phases of a rocprofv3 kernel trace (markdown) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 512 MiB (to scale HBM counters) and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(128 * 2 ** 20, dtype=torch.float32, device="cuda")
@@ -489,6 +624,15 @@ def main():
     import torch
     import paper_2202_07663_amd as G
 
+    if args.c4_only:
+        import synth
+        print(json.dumps(_finite(c4_bench(G, synth.spec_c2())), allow_nan=False), flush=True)
+        return
+    if args.serve_only:
+        r = serving_bench(args.serve_systems, args.serve_steps, small=args.serve_only == "small",
+                          tiny=args.serve_only == "tiny")
+        print(json.dumps(_finite({"serving_" + args.serve_only: r}), allow_nan=False), flush=True)
+        return
     if args.serve_poisson_only:
         r = serving_poisson_bench(args.serve_systems, args.serve_steps)
         print(json.dumps(_finite({"serving_poisson": r}), allow_nan=False), flush=True)
@@ -595,34 +739,7 @@ def main():
         out["serving_tiny"] = serving_bench(args.serve_systems, args.serve_steps, tiny=True)
     if not args.no_pipeline:
         import synth
-        # the whole fit of the 60x60 EPL + shapelet system: 4096 starts, VI 1000 x 1000, HMC
-        # 64 chains x (250 + 750) trajectories x 10 leapfrog steps. At this signal-to-noise
-        # (sigma_bkg 0.1, t_exp 1000 s) and d = 51 the multi-start Adam needs ~1e4 steps to
-        # reach the global mode; Table 1's 300 steps are run and reported beside it.
-        obs0, truth0 = stored(spec, 0)
-        m0 = G.Model.from_spec(spec, obs0)
-        t0 = time.perf_counter()
-        r300 = G.fit(m0, 4096, 300, synth.fit_priors(spec), seed=0)
-        torch.cuda.synchronize()
-        map300 = {"K": 300, "P": 4096, "chi2nu": round(r300["chi2nu"], 4),
-                  "seconds": round(time.perf_counter() - t0, 3)}
-        t0 = time.perf_counter()
-        r_map = G.fit(m0, 4096, 10000, synth.fit_priors(spec), seed=0)
-        torch.cuda.synchronize()
-        map_res = (r_map, time.perf_counter() - t0)
-        m0.close()
-        out["c4_pipeline"] = dict(workload="epl60_s0", map_at_table1_budget=map300,
-                                  **pipeline_bench(spec, obs0, truth0, n_map=4096, k_map=10000,
-                                                   n_vi=1000, k_vi=1000, chains=64, L=10,
-                                                   n_burn=250, n_samples=750,
-                                                   adapt_length=False, map_result=map_res))
-        # the same MAP point with a longer surrogate fit (Table 1's 1000 iterations at 1e-3
-        # cannot shrink the surrogate from sd 1e-3 to this posterior's widths of 1e-4 and
-        # below) and longer chains
-        out["c4_pipeline_long"] = dict(workload="epl60_s0", **pipeline_bench(
-            spec, obs0, truth0, n_map=4096, k_map=10000, n_vi=1000, k_vi=6000, chains=64, L=10,
-            n_burn=1000, n_samples=1000, adapt_length=False, vi_lr=3e-3, vi_warmup=300,
-            map_result=map_res))
+        out.update(c4_bench(G, spec))
         sp = synth.spec_paper80()
         out["pipeline"] = dict(workload="paper80_s6", **pipeline_bench(
             sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=1000, chains=50, L=5))

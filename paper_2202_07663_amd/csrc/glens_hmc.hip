@@ -330,12 +330,24 @@ struct gl_hmc {
   int max_leapfrog = 1000;
   long long leapfrogs = 0;  // leapfrog steps run by gl_hmc_run
   float T_fixed = 0.f, eps_fixed = 0.f;  // cached once adaptation has ended
+  float T0 = 0.f, eps0 = 0.f;            // the values before the first update
+  float* te_host = nullptr;  // pinned: (T, eps) after trajectory j's update, in slot j & 1
+  hipEvent_t te_ev[2] = {nullptr, nullptr};  // the copies into each slot
   float target = 0.75f;
   uint64_t seed = 0;
   char* base = nullptr;
   HmcArgs a{};
   FitBuffers fb;  // holds the priors (and unused fit arrays)
 };
+
+static void hmc_free(gl_hmc* h) {
+  if (h->base) (void)hipFree(h->base);
+  if (h->te_host) (void)hipHostFree(h->te_host);
+  for (hipEvent_t e : h->te_ev)
+    if (e) (void)hipEventDestroy(e);
+  fit_buffers_free(h->fb);
+  delete h;
+}
 
 static int hmc_launch1(void (*k)(HmcArgs), const HmcArgs& a, int n, int threads, hipStream_t st) {
   hipLaunchKernelGGL(k, dim3((n + threads - 1) / threads), dim3(threads), 0, st, a);
@@ -427,16 +439,26 @@ static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
   HmcArgs& a = h->a;
   int L = h->L;
   if (a.adapt_len) {
-    // L = ceil(u T / eps) with the jitter u shared by all chains; T and eps live on the
-    // device and change while they adapt, so they are read back until adaptation ends
+    // L = ceil(u T / eps) with the jitter u shared by all chains. T and eps adapt on the
+    // device; trajectory k takes them as they stood after trajectory k - 2's update (the
+    // initial values for k < 2). Each update is copied to pinned memory behind it, so the
+    // host waits only for a trajectory that is over while the next one is already queued,
+    // and the stream never drains between trajectories.
     float T = h->T_fixed, eps = h->eps_fixed;
-    if (h->done < h->n_adapt + 1 || !(T > 0.f)) {
-      GL_HIP(hipMemcpyAsync(&T, a.T, sizeof(float), hipMemcpyDeviceToHost, st));
-      GL_HIP(hipMemcpyAsync(&eps, a.eps, sizeof(float), hipMemcpyDeviceToHost, st));
-      GL_HIP(hipStreamSynchronize(st));
-      if (h->done >= h->n_adapt) {
-        h->T_fixed = T;
-        h->eps_fixed = eps;
+    if (!(T > 0.f)) {
+      const int j = std::min(h->done - 2, h->n_adapt - 1);  // the last update that counts
+      if (j < 0) {
+        T = h->T0;
+        eps = h->eps0;
+      } else {
+        const int slot = j & 1;
+        GL_HIP(hipEventSynchronize(h->te_ev[slot]));
+        T = h->te_host[2 * slot];
+        eps = h->te_host[2 * slot + 1];
+        if (j == h->n_adapt - 1) {  // the final values
+          h->T_fixed = T;
+          h->eps_fixed = eps;
+        }
       }
     }
     const double u = halton2(h->done + 1);
@@ -452,6 +474,13 @@ static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
     rc = hmc_launch1(hmc_mean_kernel, a, kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_finish_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_adapt_kernel, a, 1, 64, st);
+  if (!rc && a.adapt_len && h->done < h->n_adapt) {  // this trajectory updated T and eps
+    const int slot = h->done & 1;
+    GL_HIP(hipMemcpyAsync(h->te_host + 2 * slot, a.T, sizeof(float), hipMemcpyDeviceToHost, st));
+    GL_HIP(hipMemcpyAsync(h->te_host + 2 * slot + 1, a.eps, sizeof(float), hipMemcpyDeviceToHost,
+                          st));
+    GL_HIP(hipEventRecord(h->te_ev[slot], st));
+  }
   if (!rc) h->done++;
   return rc;
 }
@@ -534,9 +563,13 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
                        sizeof(double) * (2 * cd + 4 * C + 12 + 2 * d) +
                        sizeof(float) * size_t(o->n_samples) * cd + 256 * 24;
   if (!rc && hipMalloc(&h->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
+  if (!rc && hipHostMalloc(&h->te_host, 4 * sizeof(float), hipHostMallocDefault) != hipSuccess)
+    rc = set_error(GL_E_NOMEM, "hipHostMalloc failed");
+  for (int i = 0; i < 2 && !rc; ++i)
+    if (hipEventCreateWithFlags(&h->te_ev[i], hipEventDisableTiming) != hipSuccess)
+      rc = set_error(GL_E_DEVICE, "hipEventCreate failed");
   if (rc) {
-    fit_buffers_free(h->fb);
-    delete h;
+    hmc_free(h);
     return rc;
   }
   char* q = h->base;
@@ -595,6 +628,8 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
             hipMemcpy(a.stats, st0, sizeof(st0), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(a.eps, &eps0, sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
   const float T0 = float(o->n_leapfrog) * o->step_size;
+  h->T0 = T0;
+  h->eps0 = eps0;
   const double la0[4] = {std::log(double(T0)), 0.0, 0.0, std::log(double(T0))};
   ok = ok && hipMemcpy(a.T, &T0, sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(a.la, la0, sizeof(la0), hipMemcpyHostToDevice) == hipSuccess;
@@ -603,9 +638,7 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   if (!rc) rc = hmc_launch1(z0 ? hmc_round_kernel : hmc_start_kernel, a, int(cd), 256, st);
   if (!rc) rc = hmc_gradient(h, 0.f, 0, st);
   if (rc) {
-    (void)hipFree(h->base);
-    fit_buffers_free(h->fb);
-    delete h;
+    hmc_free(h);
     return rc;
   }
   *out = h;
@@ -616,9 +649,7 @@ int gl_hmc_destroy(gl_hmc* h) {
   clear_error();
   if (!h) return GL_OK;
   (void)hipDeviceSynchronize();
-  (void)hipFree(h->base);
-  fit_buffers_free(h->fb);
-  delete h;
+  hmc_free(h);
   return GL_OK;
 }
 
