@@ -104,20 +104,24 @@ int gl_model_nparams(const gl_model* model, int* d);
 int gl_model_reserve(gl_model* model, int P, int with_fit);
 
 /* Diagnostic: how a call with P parameter vectors is split on this model (no device work).
- *   psf_path:  GL_PSF_MFMA (matrix cores, one workgroup per vector: P >= 512, K <= 21, the
- *              image in at most 64 tiles of 16 rows), GL_PSF_VALU (vector ALUs, one
- *              workgroup per vector) or GL_PSF_BANDED (vector ALUs, row bands of the image
- *              per vector, for P < 512);
+ *   psf_path:  GL_PSF_MFMA (matrix cores, one workgroup per vector: K <= 21, the image in
+ *              at most 64 tiles of 16 rows, and one band: P >= 512 or at most 8 rows),
+ *              GL_PSF_VALU (vector ALUs, one workgroup per vector) or GL_PSF_BANDED (vector
+ *              ALUs, row bands of the image per vector, for P < 512);
  *   tiles, fwd_tiles: sub-pixel work tiles per vector of the adjoint and the forward pass;
  *   bands:     row bands of the PSF pass (1 unless banded);
  *   workspace_bytes: device work space of a likelihood call at this P (gl_model_reserve);
  *   workspace_reserved: what the model holds now;
- *   noalloc_max_P: the largest P gl_loglik_grad_noalloc accepts on this model. */
+ *   noalloc_max_P: the largest P gl_loglik_grad_noalloc accepts on this model;
+ *   band_split: lanes that share one strip's PSF columns in the banded pass (1, 2 or 4:
+ *              more than 1 only when the pass would have fewer work items than the GPU
+ *              has lanes, P below about 100 at 60 x 60 pixels). */
 enum { GL_PSF_MFMA = 0, GL_PSF_VALU = 1, GL_PSF_BANDED = 2 };
 typedef struct gl_plan {
   int psf_path, tiles, fwd_tiles, bands;
   size_t workspace_bytes, workspace_reserved;
   int noalloc_max_P;
+  int band_split;
 } gl_plan;
 int gl_model_plan(const gl_model* model, int P, gl_plan* out);
 

@@ -123,13 +123,14 @@ class Model:
         check(lib().gl_model_reserve(self._h, int(P), int(with_fit)))
 
     def plan(self, P: int) -> dict:
-        """How a call with P vectors is split: PSF path, tiles, bands, work-space bytes."""
+        """How a call with P vectors is split: PSF path, tiles, bands (and the lanes sharing a
+        strip's PSF columns in the banded pass), work-space bytes."""
         r = _lib.Plan()
         check(lib().gl_model_plan(self._h, int(P), ctypes.byref(r)))
         return {"psf_path": self.PSF_PATHS[r.psf_path], "tiles": r.tiles,
                 "fwd_tiles": r.fwd_tiles, "bands": r.bands,
                 "workspace_bytes": r.workspace_bytes, "workspace_reserved": r.workspace_reserved,
-                "noalloc_max_P": r.noalloc_max_P}
+                "noalloc_max_P": r.noalloc_max_P, "band_split": r.band_split}
 
     def simulate(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
         theta = self._theta(theta)

@@ -95,7 +95,8 @@ GL_PSF_MFMA, GL_PSF_VALU, GL_PSF_BANDED = 0, 1, 2
 class Plan(ctypes.Structure):
     _fields_ = [("psf_path", ctypes.c_int), ("tiles", ctypes.c_int), ("fwd_tiles", ctypes.c_int),
                 ("bands", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
-                ("workspace_reserved", ctypes.c_size_t), ("noalloc_max_P", ctypes.c_int)]
+                ("workspace_reserved", ctypes.c_size_t), ("noalloc_max_P", ctypes.c_int),
+                ("band_split", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

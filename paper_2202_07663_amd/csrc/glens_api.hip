@@ -328,7 +328,7 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   s.seed = ws.seed;
   s.beta = ws.beta;
   s.lpart = ws.lpart;
-  conv_bands(P, c.H, &s.bands, &s.band_rows);
+  conv_bands(P, c.H, c.W, &s.bands, &s.band_rows, &s.band_split);
   // matrix-core PSF pass for whole-image launches when the image's tiles and LDS fit; the
   // choice depends on this system alone, so its results do not depend on its launch partners
   const MfmaGeom q = mfma_geom(c.H, c.W, c.K);
@@ -337,7 +337,7 @@ SysDesc make_sys(const SystemData& sd, const Workspace& ws, int P, int tiles) {
   return s;
 }
 
-void conv_bands(int P, int H, int* bands, int* band_rows) {
+void conv_bands(int P, int H, int W, int* bands, int* band_rows, int* split) {
   // aim at >= 512 workgroups in the PSF pass; bands of whole strips, at most kConvMaxBands
   const int nstrip = (H + kConvRows - 1) / kConvRows;
   const int want = P >= 512 ? 1 : (512 + std::max(P, 1) - 1) / std::max(P, 1);
@@ -345,6 +345,14 @@ void conv_bands(int P, int H, int* bands, int* band_rows) {
   const int spb = (nstrip + b - 1) / b;  // strip rows per band
   *band_rows = spb * kConvRows;
   *bands = (H + *band_rows - 1) / *band_rows;
+  // small batches: split each strip's PSF columns over 2 or 4 lanes until the pass has about
+  // one work item per lane of the GPU (256 CUs x 256 lanes), so that the per-lane chains of
+  // K^2 kConvRows FMAs shorten; a one-band system keeps 1 (its bits then equal the whole-image
+  // kernel's)
+  const size_t items = size_t(P) * nstrip * W;
+  int g = 1;
+  while (*bands > 1 && g < 4 && items * g < size_t(256) * 256) g *= 2;
+  *split = g;
 }
 
 int subpix_key(const ModelCfg& c) { return (c.mass * 2 + c.lens_light) * 16 + (c.nmax + 1); }
@@ -634,6 +642,7 @@ int gl_model_plan(const gl_model* m, int P, gl_plan* out) {
                                          beta_per_particle(c));
   out->workspace_reserved = m->ws.bytes;
   out->noalloc_max_P = noalloc_max_particles(c);
+  out->band_split = s.band_split;
   return GL_OK;
 }
 

@@ -340,30 +340,48 @@ GL_HD void decode_floor(const SysDesc& s, PConst& c) {
   }
 }
 
-// Light constants (lens light, source Sersic, shapelet coefficients) of one vector.
-GL_HD void decode_lights(const float* th, int mass, int shear, int lens_light, int nmax,
-                         PConst& c) {
-  int p = mass_param_count(mass, shear);
-  c.lxs = c.lys = 0.0;
-  if (lens_light) {
-    decode_light(th + p, c.lens);
-    c.lxs = th[p + 4];
-    c.lys = th[p + 5];
-    p += 7;
+// Orders (n1, n2) of shapelet coefficient q: q runs over n = n1 + n2 = 0, 1, ... and, within
+// one n, over n2 = 0 .. n.
+GL_HD void shapelet_orders(int q, int& n1, int& n2) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 <= q) ++n;
+  n2 = q - n * (n + 1) / 2;
+  n1 = n - n2;
+}
+
+// Light constants (lens light, source Sersic, shapelet coefficients) of one vector, spread
+// over the lanes of the prologue: lane 1 the lens light, lane 2 the source, lane 3 the
+// shapelet scale, lanes 3 .. 3 + M - 1 one shapelet coefficient each (M = (n_max + 1)
+// (n_max + 2) / 2 <= 45). Every field is written by exactly one lane.
+GL_HD void decode_lights_lane(const float* th, int mass, int shear, int lens_light, int nmax,
+                              PConst& c, int lane) {
+  const int pl = mass_param_count(mass, shear);        // lens light
+  const int ps = pl + (lens_light ? 7 : 0);            // source Sersic
+  const int pb = ps + 7;                               // shapelet scale, then coefficients
+  if (lane == 1) {
+    c.lxs = c.lys = 0.0;
+    if (lens_light) {
+      decode_light(th + pl, c.lens);
+      c.lxs = th[pl + 4];
+      c.lys = th[pl + 5];
+    }
+  } else if (lane == 2) {
+    decode_light(th + ps, c.src);
+    c.sxs = th[ps + 4];
+    c.sys = th[ps + 5];
   }
-  decode_light(th + p, c.src);
-  c.sxs = th[p + 4];
-  c.sys = th[p + 5];
-  p += 7;
-  if (nmax >= 0) {
-    const double beta = th[p++];
+  if (nmax < 0) return;
+  const int q = lane - 3, M = (nmax + 1) * (nmax + 2) / 2;
+  if (q < 0 || q >= M) return;
+  const double beta = th[pb];
+  if (q == 0) {
     c.beta = float(beta);
     c.inv_beta = float(1.0 / beta);
-    const double f = 0.56418958354775628 / beta;  // 1 / (beta sqrt(pi))
-    for (int n = 0, k = 0; n <= nmax; ++n)
-      for (int n2 = 0; n2 <= n; ++n2, ++k)
-        c.shp[k] = float(double(th[p + k]) * (f * hermite_scale(n - n2, n2)));
   }
+  const double f = 0.56418958354775628 / beta;  // 1 / (beta sqrt(pi))
+  int n1, n2;
+  shapelet_orders(q, n1, n2);
+  c.shp[q] = float(double(th[pb + 1 + q]) * (f * hermite_scale(n1, n2)));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -405,6 +423,24 @@ GL_HD double pow_table_entry(double t, double log2B, int i) {
   double a = exp2(-0.5 * t * log2(mj));
   for (int q = 1; q <= k; ++q) a *= (-0.5 * t - (q - 1)) / (q * mj);
   return a;
+}
+
+// The power tables shared by `nl` lanes (this one is lane l of them): the exponent entries
+// round-robin, and the sixteen segments' Taylor coefficients one segment per lane on the last
+// kPowSeg lanes (each segment's coefficients by the recursion of pow_table_entry, the same
+// operations in the same order).
+GL_HD void pow_tables_lane(double t, double log2B, int l, int nl, double* pw) {
+  for (int i = l; i < kPowExp; i += nl) pw[i] = pow_table_entry(t, log2B, i);
+  const int j = l - (nl - kPowSeg);
+  if (j < 0) return;
+  double* seg = pw + kPowExp + 8 * j;
+  const double mj = 1.0 + (j + 0.5) / kPowSeg;
+  double a = exp2(-0.5 * t * log2(mj));
+  seg[0] = a;
+  for (int q = 1; q < 8; ++q) {
+    if (q <= kPowDeg) a *= (-0.5 * t - (q - 1)) / (q * mj);
+    seg[q] = q <= kPowDeg ? a : 0.0;
+  }
 }
 
 // A = B^t |w|^-t = B^t (|w|^2)^(-t/2) from the particle's power tables (staged in LDS): with
@@ -862,14 +898,16 @@ GL_HD int map_gradient(const PConst& c, const double* a, int mass, int shear, in
   }
   light_grad(c.src, a + A_SRC, gr + j);
   j += 7;
-  if (nmax >= 0) {
-    gr[j++] = float(a[A_SHP_BETA]);
-    const double f = double(c.inv_beta) * kInvSqrtPi;
-    for (int n = 0, q = 0; n <= nmax; ++n)
-      for (int n2 = 0; n2 <= n; ++n2, ++q)
-        gr[j++] = float(a[A_SHP_C + q] * f * hermite_scale(n - n2, n2));
-  }
+  if (nmax >= 0) gr[j++] = float(a[A_SHP_BETA]);
   return j;
+}
+
+// Gradient component of shapelet coefficient q (0 <= q < M), whose slot in the gradient
+// follows those of map_gradient.
+GL_HD float shapelet_coef_grad(const PConst& c, const double* a, int q) {
+  int n1, n2;
+  shapelet_orders(q, n1, n2);
+  return float(a[A_SHP_C + q] * (double(c.inv_beta) * kInvSqrtPi) * hermite_scale(n1, n2));
 }
 
 }  // namespace glens

@@ -121,7 +121,7 @@ inline int blocks_subpix_fwd(const SysDesc& s) { return s.P * s.ftiles; }
 inline int blocks_conv(const SysDesc& s) { return s.P; }
 inline int blocks_conv_band(const SysDesc& s) { return s.P * s.bands; }
 // Row bands of the PSF pass for P particles of an H-row image (1: the whole-image kernel).
-void conv_bands(int P, int H, int* bands, int* band_rows);
+void conv_bands(int P, int H, int W, int* bands, int* band_rows, int* split);
 
 // Run the forward (+adjoint) pipeline for a group of systems sharing key and PSF size.
 // mode: 0 image, 1 log L, 2 log L + gradient.

@@ -26,12 +26,15 @@ constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
 constexpr int kConvMaxStrips = 8;  // strips per lane: (H/8 rounded up) * W <= 8 * 256
 
 // ------------------------------------------------------------------------------------------
-// prologue: one 64-lane block per particle. Lane 0 decodes the mass, lane 1 the lights
-// while the lanes compute the series ratios in parallel; lane 0 then forms the running
-// product (in the same order as a serial loop) and the lanes store the coefficients.
+// prologue: one 64-lane block per particle. Lane 0 decodes the mass, lanes 1 and 2 the
+// light profiles and lanes 3 .. one shapelet coefficient each, while lanes 1 .. compute the
+// series ratios; lane 0 then forms the running product (in the same order as a serial loop)
+// while lane 63 looks for the floored sub-pixel and the others fill the power tables; last,
+// the lanes store the series coefficients.
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
-  static_assert(kMaxTerms <= 64, "one lane per series term");
+  static_assert(kMaxTerms <= 63, "one lane per series term, lane 63 free");
+  static_assert(3 + kMaxShp <= 64, "one lane per shapelet coefficient");
   __shared__ float th[kMaxParams];
   __shared__ double s_ratio[kMaxTerms], s_dlog[kMaxTerms], s_cn[kMaxTerms], s_ds[kMaxTerms];
   const int si = find_sys(g, blockIdx.x);
@@ -49,14 +52,15 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
   }
   __syncthreads();
   PConst& c = s.pc[p];
-  if (lane == 0) {
-    decode_mass(th, s.mass, s.shear, c);
-    decode_floor(s, c);
-  }
-  if (lane == 1) decode_lights(th, s.mass, s.shear, s.lens_light, s.nmax, c);
+  // the decode, spread over lanes: the mass on lane 0, the lights and shapelet coefficients
+  // on lanes 1 ..; the series ratios on lanes 1 .. kMaxTerms - 1
+  if (lane == 0) decode_mass(th, s.mass, s.shear, c);
+  decode_lights_lane(th, s.mass, s.shear, s.lens_light, s.nmax, c, lane);
   const double t = (s.mass == 1) ? double(th[1]) - 1.0 : 1.0;
   if (lane > 0 && lane < kMaxTerms) series_step(lane, t, s_ratio[lane], s_dlog[lane]);
   __syncthreads();
+  // lane 0 forms the running product; lane 63 looks for the floored sub-pixel; the others
+  // fill the power tables (all from decode_mass's constants, written before the barrier)
   if (lane == 0) {
     double cn = 1.0, dsum = 0.0;
     s_cn[0] = cn;
@@ -67,12 +71,13 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
       s_cn[n] = cn;
       s_ds[n] = dsum;
     }
+  } else if (lane == 63) {
+    decode_floor(s, c);
+  } else {
+    pow_tables_lane(c.t, log2(c.bmass), lane - 1, 62, c.pw);
   }
   __syncthreads();
   if (lane < kMaxTerms) series_store(c, lane, s_cn[lane], s_ds[lane]);
-  // power tables of the ray trace (c.t and c.bmass were written by lane 0 before the barrier)
-  const double log2B = log2(c.bmass), tt = c.t;
-  for (int i = lane; i < kPowExp + kPowSeg * 8; i += 64) c.pw[i] = pow_table_entry(tt, log2B, i);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -189,12 +194,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 template <int K>
 __device__ __forceinline__ void correlate_strip(const float* __restrict__ buf, int Hs, int i0,
                                                 int j, const float* __restrict__ taps,
-                                                float* acc) {
+                                                float* acc, int b0 = 0, int bstep = 1) {
   constexpr int R = kConvRows;
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.f;
 #pragma unroll 1
-  for (int b = 0; b < K; ++b) {
+  for (int b = b0; b < K; b += bstep) {
     const float* colp = buf + (j + b) * Hs + i0;
     float col[R + K - 1];
 #pragma unroll
@@ -596,11 +601,24 @@ conv_mfma_kernel(Group g) {
 //   conv_band_adj_kernel   the correlation of the seed with the PSF; the first band of a
 //                          particle also adds the likelihood partials (band order);
 //   conv_band_sum_kernel   the same addition when there is no adjoint pass.
-// Per pixel the arithmetic is that of conv_kernel; only the order of the log L sum differs.
+// With band_split = 1 the arithmetic per pixel is that of conv_kernel (only the order of the
+// log L sum differs). Very small batches split each strip's K PSF columns over G = 2 or 4
+// adjacent lanes (columns g, g + G, ...), whose partial sums are then added by an xor
+// butterfly: more lanes in flight and K^2 kConvRows / G FMAs in each lane's chain.
 // ------------------------------------------------------------------------------------------
+static_assert(kConvThreads % 4 == 0, "whole lane groups of the split PSF columns");
 struct Band {
   int part, band, r0, r1, nsr, Hs;
 };
+
+// Sums a strip's partial accumulators over the G lanes that share it (adjacent lanes, G a
+// power of two <= 4, every lane of the group active); each lane ends with the full sums.
+__device__ __forceinline__ void split_sum(float* acc, int G) {
+  for (int o = 1; o < G; o <<= 1) {
+#pragma unroll
+    for (int r = 0; r < kConvRows; ++r) acc[r] += __shfl_xor(acc[r], o, 64);
+  }
+}
 
 __device__ __forceinline__ Band band_of(const SysDesc& s, int local, int K) {
   Band b;
@@ -640,10 +658,20 @@ __global__ void __launch_bounds__(kConvThreads) conv_band_kernel(Group g) {
   const int W = s.W, HW = s.H * W, mode = s.mode;
   load_band<K>(s.m0 + (size_t)b.part * HW, s, b, lds);
   double ll = 0.0, c2 = 0.0;
-  for (int sidx = threadIdx.x; sidx < b.nsr * W; sidx += blockDim.x) {
-    const int st = sidx / W, j = sidx - st * W, i0 = st * R;
+  // work items (strip, column, PSF-column share); the G lanes of one strip are adjacent, and
+  // blockDim and the item count are multiples of G, so they run the loop together
+  const int G = s.band_split, gs = G >> 1;  // G = 1, 2, 4: log2 G = G / 2
+  for (int sidx = threadIdx.x; sidx < b.nsr * W * G; sidx += blockDim.x) {
+    const int item = sidx >> gs, g0 = sidx & (G - 1);
+    const int st = item / W, j = item - st * W, i0 = st * R;
     float acc[R];
-    correlate_strip<K>(lds, b.Hs, i0, j, s.psf_flip, acc);
+    if (G == 1) {
+      correlate_strip<K>(lds, b.Hs, i0, j, s.psf_flip, acc);
+    } else {
+      correlate_strip<K>(lds, b.Hs, i0, j, s.psf_flip, acc, g0, G);
+      split_sum(acc, G);
+      if (g0 != 0) continue;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = b.r0 + i0 + r;
@@ -700,10 +728,18 @@ __global__ void __launch_bounds__(kConvThreads) conv_band_adj_kernel(Group g) {
   const int W = s.W, HW = s.H * W;
   if (b.band == 0 && threadIdx.x == 0) band_totals(s, b.part);
   load_band<K>(s.seed + (size_t)b.part * HW, s, b, lds);
-  for (int sidx = threadIdx.x; sidx < b.nsr * W; sidx += blockDim.x) {
-    const int st = sidx / W, j = sidx - st * W, i0 = st * R;
+  const int G = s.band_split, gs = G >> 1;  // G = 1, 2, 4: log2 G = G / 2
+  for (int sidx = threadIdx.x; sidx < b.nsr * W * G; sidx += blockDim.x) {
+    const int item = sidx >> gs, g0 = sidx & (G - 1);
+    const int st = item / W, j = item - st * W, i0 = st * R;
     float acc[R];
-    correlate_strip<K>(lds, b.Hs, i0, j, s.psf, acc);
+    if (G == 1) {
+      correlate_strip<K>(lds, b.Hs, i0, j, s.psf, acc);
+    } else {
+      correlate_strip<K>(lds, b.Hs, i0, j, s.psf, acc, g0, G);
+      split_sum(acc, G);
+      if (g0 != 0) continue;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = b.r0 + i0 + r;
@@ -912,10 +948,14 @@ __global__ void __launch_bounds__(64) finalize_kernel(Group g) {
   // lane 0 maps the sums (to LDS, not to a lane-private array the compiler would spill);
   // the lanes then check and store the components
   __shared__ float gr[kMaxParams];
-  __shared__ int s_j;
-  if (threadIdx.x == 0) s_j = map_gradient(c, a, s.mass, s.shear, s.lens_light, s.nmax, gr);
+  // the shapelet coefficients' components (if any) follow the others, one per lane
+  __shared__ int s_j0;
+  if (threadIdx.x == 0) s_j0 = map_gradient(c, a, s.mass, s.shear, s.lens_light, s.nmax, gr);
   __syncthreads();
-  const int j = s_j;
+  const int M = s.nmax < 0 ? 0 : (s.nmax + 1) * (s.nmax + 2) / 2;
+  for (int q = threadIdx.x; q < M; q += blockDim.x) gr[s_j0 + q] = shapelet_coef_grad(c, a, q);
+  __syncthreads();
+  const int j = s_j0 + M;
   int bad = 0;
   for (int q = threadIdx.x; q < j; q += blockDim.x) bad |= !isfinite(gr[q]);
   const bool ok = isfinite(s.logl[p]) && !__any(bad);

@@ -136,6 +136,7 @@ struct SysDesc {
   int mode;            // conv kernel: 0 image, 1 log L, 2 log L + adjoint seed
   int bands;           // banded PSF pass: row bands per particle (1: whole image)
   int band_rows;       // rows per band (a multiple of the strip height)
+  int band_split;      // banded pass: lanes that share one strip's PSF columns (1, 2 or 4)
   const float* obs;
   const float* psf;      // K*K
   const float* psf_flip; // K*K, flipped in both axes

@@ -8,8 +8,11 @@
 //            z_s = mu + L eps_s, rounded to FP32 for the likelihood pipeline;
 //   pipeline log L and d log L / d theta at g(z_s) for every sample in one batched launch;
 //   grad     one block per sample: f_s = -log p~(z_s | I) and grad f_s (prior, bijector);
-//   update   one lane per entry of x: the pathwise gradient estimate (mean over the samples
-//            with a finite objective, in sample order, FP64) of
+//   reduce   one block per chunk of kViChunk samples (staged in LDS): per entry of x the
+//            chunk's sum (in sample order, FP64) of (grad f)_i or (grad f)_i eps_j over its
+//            samples with a finite objective, and the chunk's sum of f and sample count;
+//   update   one lane per entry of x: the chunks' sums added in chunk order give the
+//            pathwise gradient estimate (mean over the samples with a finite objective) of
 //              mu_i: E[(grad f)_i],  L_ij (i > j): E[(grad f)_i eps_j],
 //              v_ii = log L_ii: L_ii E[(grad f)_i eps_i] - 1,
 //            then Adam at the iteration's learning rate. x is double-buffered so that every
@@ -31,6 +34,7 @@
 namespace glens {
 
 constexpr int kViThreads = 64;
+constexpr int kViChunk = 32;  // samples per block of the reduction
 constexpr uint32_t kViDrawTag = 0x76690000u;
 constexpr uint32_t kViSampleTag = 0x76697371u;
 
@@ -51,8 +55,24 @@ struct ViArgs {
   const float* grad;
   const float* theta;
   double* loss;        // [K] loss history
+  double* part;        // [chunks][d + nc + 2] per-chunk sums, then the chunk's sum of f and count
   uint32_t seed_lo, seed_hi;
 };
+
+// Row and column of entry q of x: (q, -1) for mu_q, else the lower-triangle position of
+// v_(q - d) (row-major: r = i(i+1)/2 + j).
+__device__ __forceinline__ void vi_entry(int q, int d, int& i, int& j) {
+  if (q < d) {
+    i = q;
+    j = -1;
+    return;
+  }
+  const int r = q - d;
+  i = int((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= r) ++i;
+  while (i * (i + 1) / 2 > r) --i;
+  j = r - i * (i + 1) / 2;
+}
 
 __device__ __forceinline__ double chol_entry(const double* v, int i, int j) {
   const double e = v[i * (i + 1) / 2 + j];
@@ -111,33 +131,62 @@ __global__ void __launch_bounds__(kViThreads) vi_grad_kernel(ViArgs a) {
   }
 }
 
-// Gradient estimate and Adam update of one entry of x (and the loss, lane 0).
-__global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a) {
+// Per-chunk sums of the gradient estimate's terms (one block per kViChunk samples).
+__global__ void __launch_bounds__(256) vi_reduce_kernel(ViArgs a) {
+  __shared__ double s_g[kViChunk][kMaxParams], s_e[kViChunk][kMaxParams];
+  const int d = a.d, nx = a.d + a.nc;
+  const int s0 = blockIdx.x * kViChunk, ns = min(kViChunk, a.n - s0);
+  for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+    const int t = idx / d, j = idx - t * d;
+    const size_t o = size_t(s0 + t) * d + j;
+    const bool ok = isfinite(a.f[s0 + t]);  // a sample without a finite objective adds 0
+    s_g[t][j] = ok ? double(a.g[o]) : 0.0;
+    s_e[t][j] = ok ? a.eps[o] : 0.0;
+  }
+  __syncthreads();
+  double* out = a.part + size_t(blockIdx.x) * (nx + 2);
+  for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+    int i, j;
+    vi_entry(q, d, i, j);
+    double sum = 0.0;
+    if (j < 0) {
+      for (int t = 0; t < ns; ++t) sum += s_g[t][i];
+    } else {
+      for (int t = 0; t < ns; ++t) sum += s_g[t][i] * s_e[t][j];
+    }
+    out[q] = sum;
+  }
+  if (threadIdx.x == 0) {
+    double fsum = 0.0;
+    int nok = 0;
+    for (int t = 0; t < ns; ++t) {
+      const double fs = a.f[s0 + t];
+      if (!isfinite(fs)) continue;
+      ++nok;
+      fsum += fs;
+    }
+    out[nx] = fsum;
+    out[nx + 1] = nok;
+  }
+}
+
+// Gradient estimate and Adam update of one entry of x (and the loss, lane 0), from the
+// chunks' sums.
+__global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a, int chunks) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int d = a.d, nx = a.d + a.nc;
   if (q >= nx) return;
   const double* v = a.x + d;
   int i, j;
-  if (q < d) {
-    i = q;
-    j = -1;
-  } else {  // row-major lower triangle: r = i(i+1)/2 + j
-    const int r = q - d;
-    i = int((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= r) ++i;
-    while (i * (i + 1) / 2 > r) --i;
-    j = r - i * (i + 1) / 2;
+  vi_entry(q, d, i, j);
+  double sum = 0.0, fsum = 0.0, nokd = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    const double* pc = a.part + size_t(c) * (nx + 2);
+    sum += pc[q];
+    fsum += pc[nx];
+    nokd += pc[nx + 1];
   }
-  double sum = 0.0, fsum = 0.0;
-  int nok = 0;
-  for (int s = 0; s < a.n; ++s) {
-    const double fs = a.f[s];
-    if (!isfinite(fs)) continue;
-    ++nok;
-    const double gi = a.g[size_t(s) * d + i];
-    sum += j < 0 ? gi : gi * a.eps[size_t(s) * d + j];
-    fsum += fs;
-  }
+  const int nok = int(nokd);
   if (nok == 0) {  // no usable sample: keep the state
     a.x_new[q] = a.x[q];
     if (q == 0) a.loss[a.k] = NAN;
@@ -238,8 +287,10 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
   if ((rc = run_group(g, subpix_key(c), c.K, 2, st))) return rc;
   hipLaunchKernelGGL(vi_grad_kernel, dim3(v->n), dim3(kViThreads), 0, st, a);
   if ((rc = vi_check_launch())) return rc;
-  const int nx = v->d + v->nc;
-  hipLaunchKernelGGL(vi_update_kernel, dim3((nx + 255) / 256), dim3(256), 0, st, a);
+  const int nx = v->d + v->nc, chunks = (v->n + kViChunk - 1) / kViChunk;
+  hipLaunchKernelGGL(vi_reduce_kernel, dim3(chunks), dim3(256), 0, st, a);
+  if ((rc = vi_check_launch())) return rc;
+  hipLaunchKernelGGL(vi_update_kernel, dim3((nx + 255) / 256), dim3(256), 0, st, a, chunks);
   if ((rc = vi_check_launch())) return rc;
   v->cur = 1 - v->cur;
   v->k++;
@@ -286,7 +337,8 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
                          beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(v->fb, n, d, pri.data());
   const size_t nd = size_t(n) * d;
-  const size_t bytes = sizeof(double) * (4 * size_t(nx) + nd + n + o->K) +
+  const size_t npart = size_t((n + kViChunk - 1) / kViChunk) * (nx + 2);
+  const size_t bytes = sizeof(double) * (4 * size_t(nx) + nd + n + o->K + npart) +
                        sizeof(float) * 2 * nd + 256 * 12;
   if (!rc && hipMalloc(&v->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
   if (rc) {
@@ -312,6 +364,7 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
   a.eps = reinterpret_cast<double*>(take(sizeof(double) * nd));
   a.f = reinterpret_cast<double*>(take(sizeof(double) * n));
   a.loss = reinterpret_cast<double*>(take(sizeof(double) * o->K));
+  a.part = reinterpret_cast<double*>(take(sizeof(double) * npart));
   a.z32 = reinterpret_cast<float*>(take(sizeof(float) * nd));
   a.g = reinterpret_cast<float*>(take(sizeof(float) * nd));
   const bool defaults = o->beta1 == 0.f && o->beta2 == 0.f && o->eps == 0.f;

@@ -276,8 +276,9 @@ def test_repeat_is_bitwise_identical(glens, epl60_case):
 def test_batch_composition_invariance(glens, epl60_case):
     """At a fixed batch size, a vector's result does not depend on which other vectors share
     the launch (bitwise): the work split and every summation order depend only on the
-    model and P. Across batch sizes the sub-pixel tiling changes, so gradients agree to
-    FP32 summation-order rounding only."""
+    model and P. Across batch sizes the sub-pixel tiling changes, and so does the PSF pass's
+    summation order for very small batches (their strips' PSF columns are split over lanes),
+    so log L and the gradient agree to FP32 summation-order rounding only."""
     spec, obs, theta = epl60_case
     m = glens.Model.from_spec(spec, obs)
     a = _run(m, theta[:300])
@@ -286,7 +287,7 @@ def test_batch_composition_invariance(glens, epl60_case):
     np.testing.assert_array_equal(a[0][290:300], b[0][290:])
     np.testing.assert_array_equal(a[1][290:300], b[1][290:])
     c = _run(m, theta[290:300])
-    np.testing.assert_array_equal(a[0][290:300], c[0])
+    np.testing.assert_allclose(c[0], a[0][290:300], rtol=1e-5)
     np.testing.assert_allclose(c[1], a[1][290:300], rtol=1e-5,
                                atol=1e-5 * np.abs(a[1][290:300]).max())
 
