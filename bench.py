@@ -75,8 +75,8 @@ def flops_model(H, W, k, K, nmax, lens_light, N_mean, sie=False):
 # the translation unit the likelihood and adjoint kernels are compiled in, with every file it
 # includes: a change to any of them can change the profiled kernels' code
 KERNEL_SOURCES = ["paper_2202_07663_amd/csrc/" + f for f in (
-    "glens_api.hip", "glens_kernels.h", "glens_device.h", "glens_fit_device.h", "glens_types.h",
-    "glens_host.h")] + ["include/gl.h"]
+    "glens_api.hip", "glens_kernels.h", "glens_particle.h", "glens_device.h",
+    "glens_fit_device.h", "glens_types.h", "glens_host.h")] + ["include/gl.h"]
 
 
 def csrc_hash() -> str:

@@ -518,12 +518,15 @@ static int launch_conv_band(int K, Group& g, int mode, hipStream_t st) {
   return GL_OK;
 }
 
-int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev) {
+int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev,
+              bool prologue, bool finalize) {
   int rc;
   auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
   GL_HIP(mark(0));
-  set_blocks(g, blocks_prologue);
-  if ((rc = launch_prologue(g, st))) return rc;
+  if (prologue) {
+    set_blocks(g, blocks_prologue);
+    if ((rc = launch_prologue(g, st))) return rc;
+  }
   GL_HIP(mark(1));
   for (int i = 0; i < g.nsys; ++i) g.sys[i].mode = mode;  // the forward pass keeps beta in mode 2
   set_blocks(g, blocks_subpix_fwd);
@@ -560,6 +563,7 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev
   set_blocks(g, blocks_subpix);
   if ((rc = launch_subpix_adj(key, g, st))) return rc;
   GL_HIP(mark(4));
+  if (!finalize) return GL_OK;
   set_blocks(g, blocks_prologue);
   if ((rc = launch_finalize(g, st))) return rc;
   GL_HIP(mark(5));

@@ -12,10 +12,12 @@
 // During the first adapt_frac of burn-in the step size follows Hoffman & Gelman's dual
 // averaging towards target_accept (the paper uses 0.75 over the first 80% of burn-in); it
 // is then fixed at the averaged value. Every chain is one particle of the likelihood launch,
-// so a leapfrog step costs one batched gradient call over all chains. The per-chain kernels
-// run one 64-lane block per chain with the chain's d <= 68 coordinates in LDS. The
-// trajectory counter lives in device memory, so a trajectory's launches do not change
-// between trajectories.
+// so a leapfrog step costs one batched gradient call over all chains; the pipeline's last
+// stage (finalize), the kick and drift and the next step's decode (prologue) run fused in
+// one per-chain kernel, so that a step after the first launches the sub-pixel forward pass,
+// the PSF pass, the sub-pixel adjoint and that kernel. The per-chain kernels run one 64-lane
+// block per chain with the chain's d <= 68 coordinates in LDS. The trajectory counter lives
+// in device memory, so a trajectory's launches do not change between trajectories.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +28,7 @@
 #include "glens_fit.h"
 #include "glens_fit_device.h"
 #include "glens_host.h"
+#include "glens_particle.h"
 
 namespace glens {
 
@@ -73,11 +76,17 @@ __device__ __forceinline__ float step_size(const HmcArgs& a) {
   return a.eps_fixed > 0.f ? a.eps_fixed : *a.eps;
 }
 
-// v = chol^T x for one chain (x in LDS, v to LDS); lanes own output coordinates.
-__device__ __forceinline__ void chol_t_times(const HmcArgs& a, const float* x, float* v) {
-  for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
+// Copies the d x d factor m to LDS (the per-chain products read every entry in dependent
+// chains, where LDS reads wait far less than L2 ones); the caller synchronises the block.
+__device__ __forceinline__ void stage_factor(const float* m, int d, float* s_m) {
+  for (int q = threadIdx.x; q < d * d; q += kHmcThreads) s_m[q] = m[q];
+}
+
+// v = chol^T x for one chain (chol, x in LDS, v to LDS); lanes own output coordinates.
+__device__ __forceinline__ void chol_t_times(const float* chol, int d, const float* x, float* v) {
+  for (int j = threadIdx.x; j < d; j += kHmcThreads) {
     float s = 0.f;
-    for (int i = j; i < a.d; ++i) s += a.chol[i * a.d + j] * x[i];
+    for (int i = j; i < d; ++i) s += chol[i * d + j] * x[i];
     v[j] = s;
   }
 }
@@ -97,12 +106,14 @@ __device__ __forceinline__ void kick_drift(const HmcArgs& a, const float* s_g, f
     }
   }
   if (!drift) return;
+  __shared__ float s_chol[kMaxParams * kMaxParams];
+  stage_factor(a.chol, a.d, s_chol);
   __syncthreads();
-  chol_t_times(a, s_p, s_v);
+  chol_t_times(s_chol, a.d, s_p, s_v);
   __syncthreads();
   for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
     float s = 0.f;
-    for (int i = 0; i <= j; ++i) s += a.chol[j * a.d + i] * s_v[i];
+    for (int i = 0; i <= j; ++i) s += s_chol[j * a.d + i] * s_v[i];
     const double zn = a.z[row + j] + double(eps) * s;
     a.z[row + j] = zn;
     a.z32[row + j] = float(zn);
@@ -111,8 +122,7 @@ __device__ __forceinline__ void kick_drift(const HmcArgs& a, const float* s_g, f
 
 // log p~(z | I) and its gradient from the pipeline outputs (terms summed in parameter
 // order by lane 0), then the kick and drift of the leapfrog step.
-__global__ void __launch_bounds__(kHmcThreads) hmc_grad_move_kernel(HmcArgs a, float scale,
-                                                                    int drift) {
+__device__ __forceinline__ void grad_move(const HmcArgs& a, float scale, int drift) {
   __shared__ double s_t[kMaxParams];
   __shared__ float s_g[kMaxParams], s_p[kMaxParams], s_v[kMaxParams];
   __shared__ int s_bad;
@@ -144,13 +154,29 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_grad_move_kernel(HmcArgs a, f
   kick_drift(a, s_g, scale, drift, s_p, s_v);
 }
 
+// One block per chain: the pipeline's finalize (log L and its gradient), log p~ and its
+// gradient, the kick and, with a drift, the decode of the new position for the next step's
+// pipeline (prologue), which then starts at the sub-pixel forward pass. Two launches fewer
+// per leapfrog step than finalize, kick/drift and prologue apart, with the same arithmetic.
+__global__ void __launch_bounds__(kHmcThreads) hmc_finalize_move_kernel(SysDesc s, HmcArgs a,
+                                                                        float scale, int drift) {
+  finalize_particle(s, blockIdx.x);
+  __syncthreads();  // this chain's log L and gradient are written
+  grad_move(a, scale, drift);
+  if (!drift) return;
+  __syncthreads();  // this chain's new position is written
+  prologue_particle(s, blockIdx.x);
+}
+
 // New momentum p = chol^-T n, saved trajectory start and kinetic energy |n|^2 / 2, then the
 // first half kick and drift.
 __global__ void __launch_bounds__(kHmcThreads) hmc_begin_kernel(HmcArgs a) {
   __shared__ float s_n[kMaxParams], s_g[kMaxParams], s_p[kMaxParams], s_v[kMaxParams];
+  __shared__ float s_cit[kMaxParams * kMaxParams];
   const int c = blockIdx.x;
   const int traj = *a.traj;
   const size_t row = size_t(c) * a.d;
+  stage_factor(a.chol_it, a.d, s_cit);
   for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
     uint32_t w[4] = {uint32_t(c), uint32_t(j), uint32_t(traj), 0x6d6f6d65u};
     philox4x32_10(w, a.seed_lo, a.seed_hi);
@@ -162,7 +188,7 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_begin_kernel(HmcArgs a) {
   __syncthreads();
   for (int i = threadIdx.x; i < a.d; i += kHmcThreads) {
     float s = 0.f;
-    for (int j = i; j < a.d; ++j) s += a.chol_it[i * a.d + j] * s_n[j];
+    for (int j = i; j < a.d; ++j) s += s_cit[i * a.d + j] * s_n[j];
     a.p[row + i] = s;
   }
   if (threadIdx.x == 0) {
@@ -176,7 +202,6 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_begin_kernel(HmcArgs a) {
   kick_drift(a, s_g, 0.5f, 1, s_p, s_v);
 }
 
-// Metropolis accept / reject and the sample record.
 // Chain means of the trajectory starts and of the proposals (one lane per parameter, chains
 // in order), for the ChEES gradient.
 __global__ void __launch_bounds__(kHmcThreads) hmc_mean_kernel(HmcArgs a) {
@@ -191,6 +216,7 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_mean_kernel(HmcArgs a) {
   }
 }
 
+// Metropolis accept / reject and the sample record.
 __global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
   __shared__ float s_p[kMaxParams], s_v[kMaxParams];
   __shared__ double s_w[kMaxParams];
@@ -198,15 +224,17 @@ __global__ void __launch_bounds__(kHmcThreads) hmc_finish_kernel(HmcArgs a) {
   const int c = blockIdx.x;
   const int traj = *a.traj;
   const size_t row = size_t(c) * a.d;
+  __shared__ float s_chol[kMaxParams * kMaxParams];
+  stage_factor(a.chol, a.d, s_chol);
   for (int j = threadIdx.x; j < a.d; j += kHmcThreads) s_p[j] = a.p[row + j];
   __syncthreads();
-  chol_t_times(a, s_p, s_v);
+  chol_t_times(s_chol, a.d, s_p, s_v);
   __syncthreads();
   const bool chees = a.adapt_len && traj < a.n_adapt;
   if (chees) {  // per coordinate: (z' - zbar')_j (M^-1 p')_j, M^-1 p' = chol (chol^T p')
     for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
       float v = 0.f;
-      for (int i = 0; i <= j; ++i) v += a.chol[j * a.d + i] * s_v[i];
+      for (int i = 0; i <= j; ++i) v += s_chol[j * a.d + i] * s_v[i];
       s_w[j] = (a.z[row + j] - a.zbar[a.d + j]) * double(v);
     }
     __syncthreads();
@@ -331,6 +359,7 @@ struct gl_hmc {
   long long leapfrogs = 0;  // leapfrog steps run by gl_hmc_run
   float T_fixed = 0.f, eps_fixed = 0.f;  // cached once adaptation has ended
   float T0 = 0.f, eps0 = 0.f;            // the values before the first update
+  bool pc_ready = false;  // the chains' particle constants are those of their current z
   float* te_host = nullptr;  // pinned: (T, eps) after trajectory j's update, in slot j & 1
   hipEvent_t te_ev[2] = {nullptr, nullptr};  // the copies into each slot
   float target = 0.75f;
@@ -355,12 +384,6 @@ static int hmc_launch1(void (*k)(HmcArgs), const HmcArgs& a, int n, int threads,
   return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
 }
 
-static int hmc_chain_launch(void (*k)(HmcArgs, float, int), const HmcArgs& a, float scale,
-                            int drift, hipStream_t st) {
-  hipLaunchKernelGGL(k, dim3(a.C), dim3(kHmcThreads), 0, st, a, scale, drift);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? GL_OK : set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
-}
 
 // Lower Cholesky factor of the symmetric matrix s [d][d] (row-major, double); false unless
 // positive definite.
@@ -404,8 +427,10 @@ static int hmc_gradient(gl_hmc* h, float scale, int drift, hipStream_t st) {
   const ModelCfg& c = m->sys.cfg;
   const int tiles = choose_tiles(h->C, c.H * c.W);
   // Another call on the model may have regrown its workspace: reserve and re-read.
+  const PConst* pc_before = m->ws.pc;
   int rc = workspace_reserve(m->ws, h->C, tiles, c.H * c.W, c.d, true, beta_per_particle(c));
   if (rc) return rc;
+  if (m->ws.pc != pc_before) h->pc_ready = false;
   Group g;
   std::memset(&g, 0, sizeof(g));
   g.nsys = 1;
@@ -419,9 +444,16 @@ static int hmc_gradient(gl_hmc* h, float scale, int drift, hipStream_t st) {
   h->a.logl = m->ws.logl;
   h->a.grad = m->ws.grad;
   h->a.theta = m->ws.theta;
-  rc = run_group(g, subpix_key(c), c.K, 2, st);
+  // the previous step's fused kernel decoded the current positions unless pc_ready is false
+  rc = run_group(g, subpix_key(c), c.K, 2, st, nullptr, !h->pc_ready, false);
+  h->pc_ready = false;
   if (rc) return rc;
-  return hmc_chain_launch(hmc_grad_move_kernel, h->a, scale, drift, st);
+  hipLaunchKernelGGL(hmc_finalize_move_kernel, dim3(h->C), dim3(kHmcThreads), 0, st, g.sys[0],
+                     h->a, scale, drift);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(GL_E_DEVICE, "launch: %s", hipGetErrorString(e));
+  h->pc_ready = drift != 0;
+  return GL_OK;
 }
 
 // van der Corput sequence in base 2: the jitter of trajectory k (k >= 1).
@@ -467,6 +499,7 @@ static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
     L = int(std::min(double(h->max_leapfrog), std::max(1.0, std::isfinite(steps) ? steps : 1.0)));
   }
   h->leapfrogs += L;
+  h->pc_ready = false;  // the first half step drifts the positions
   int rc = hmc_launch1(hmc_begin_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
   for (int l = 0; !rc && l < L; ++l)
     rc = hmc_gradient(h, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);
@@ -661,6 +694,7 @@ int gl_hmc_run(gl_hmc* h, int n, void* stream) {
   if (h->done + n > total)
     return set_error(GL_E_INVALID, "%d trajectories requested, %d left", n, total - h->done);
   h->a.eps_fixed = 0.f;
+  h->pc_ready = false;  // another call on the model may have used its particle constants
   for (int i = 0; i < n; ++i) {
     int rc = hmc_trajectory(h, (hipStream_t)stream);
     if (rc) return rc;
@@ -713,6 +747,7 @@ int gl_hmc_leapfrog(gl_hmc* h, const double* z, const float* p, int L, float eps
   GL_HIP(hipMemcpyAsync(a.z, z, 2 * b, hipMemcpyDeviceToDevice, st));
   GL_HIP(hipMemcpyAsync(a.p, p, b, hipMemcpyDeviceToDevice, st));
   a.eps_fixed = eps;
+  h->pc_ready = false;  // new positions
   rc = hmc_launch1(hmc_round_kernel, a, h->C * h->d, 256, st);
   if (!rc) rc = hmc_gradient(h, 0.5f, 1, st);
   for (int l = 0; !rc && l < L; ++l) rc = hmc_gradient(h, l + 1 < L ? 1.0f : 0.5f, l + 1 < L, st);

@@ -126,7 +126,11 @@ void conv_bands(int P, int H, int W, int* bands, int* band_rows, int* split);
 // Run the forward (+adjoint) pipeline for a group of systems sharing key and PSF size.
 // mode: 0 image, 1 log L, 2 log L + gradient.
 // ev (optional): GL_NSTAGES + 1 events, recorded before the first and after every stage.
-int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev = nullptr);
+// prologue = false skips the decode (the particles' constants are already those of their
+// current parameters); finalize = false stops after the sub-pixel adjoint (the caller runs
+// finalize_particle itself, fused with its own per-particle step).
+int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev = nullptr,
+              bool prologue = true, bool finalize = true);
 
 int check_device_ptr(const void* p, const char* name);
 

@@ -17,6 +17,7 @@
 
 #include "glens_device.h"
 #include "glens_fit_device.h"
+#include "glens_particle.h"
 
 namespace glens {
 
@@ -25,59 +26,10 @@ constexpr int kConvThreads = 256;
 constexpr int kConvRows = 8;  // output rows per lane in the PSF pass
 constexpr int kConvMaxStrips = 8;  // strips per lane: (H/8 rounded up) * W <= 8 * 256
 
-// ------------------------------------------------------------------------------------------
-// prologue: one 64-lane block per particle. Lane 0 decodes the mass, lanes 1 and 2 the
-// light profiles and lanes 3 .. one shapelet coefficient each, while lanes 1 .. compute the
-// series ratios; lane 0 then forms the running product (in the same order as a serial loop)
-// while lane 63 looks for the floored sub-pixel and the others fill the power tables; last,
-// the lanes store the series coefficients.
-// ------------------------------------------------------------------------------------------
+// prologue: one 64-lane block per particle (prologue_particle)
 __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
-  static_assert(kMaxTerms <= 63, "one lane per series term, lane 63 free");
-  static_assert(3 + kMaxShp <= 64, "one lane per shapelet coefficient");
-  __shared__ float th[kMaxParams];
-  __shared__ double s_ratio[kMaxTerms], s_dlog[kMaxTerms], s_cn[kMaxTerms], s_ds[kMaxTerms];
   const int si = find_sys(g, blockIdx.x);
-  const SysDesc& s = g.sys[si];
-  const int p = blockIdx.x - g.block0[si];
-  const int d = s.d, lane = threadIdx.x;
-  for (int j = lane; j < d; j += blockDim.x) {
-    const size_t i = (size_t)p * d + j;
-    if (s.z) {
-      th[j] = bijector_fwd(s.prior[j], s.z[i]);
-      s.theta_out[i] = th[j];
-    } else {
-      th[j] = s.theta[i];
-    }
-  }
-  __syncthreads();
-  PConst& c = s.pc[p];
-  // the decode, spread over lanes: the mass on lane 0, the lights and shapelet coefficients
-  // on lanes 1 ..; the series ratios on lanes 1 .. kMaxTerms - 1
-  if (lane == 0) decode_mass(th, s.mass, s.shear, c);
-  decode_lights_lane(th, s.mass, s.shear, s.lens_light, s.nmax, c, lane);
-  const double t = (s.mass == 1) ? double(th[1]) - 1.0 : 1.0;
-  if (lane > 0 && lane < kMaxTerms) series_step(lane, t, s_ratio[lane], s_dlog[lane]);
-  __syncthreads();
-  // lane 0 forms the running product; lane 63 looks for the floored sub-pixel; the others
-  // fill the power tables (all from decode_mass's constants, written before the barrier)
-  if (lane == 0) {
-    double cn = 1.0, dsum = 0.0;
-    s_cn[0] = cn;
-    s_ds[0] = dsum;
-    for (int n = 1; n < kMaxTerms; ++n) {
-      cn *= s_ratio[n];
-      dsum += s_dlog[n];
-      s_cn[n] = cn;
-      s_ds[n] = dsum;
-    }
-  } else if (lane == 63) {
-    decode_floor(s, c);
-  } else {
-    pow_tables_lane(c.t, log2(c.bmass), lane - 1, 62, c.pw);
-  }
-  __syncthreads();
-  if (lane < kMaxTerms) series_store(c, lane, s_cn[lane], s_ds[lane]);
+  prologue_particle(g.sys[si], blockIdx.x - g.block0[si]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -902,66 +854,10 @@ subpix_adj_kernel(Group g) {
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// finalize: one 64-lane block (a single wave) per particle; lanes sum the tiles' partial
-// accumulators (in tile order), lane 0 maps them to the parameter gradient
-// ------------------------------------------------------------------------------------------
+// finalize: one 64-lane block per particle (finalize_particle)
 __global__ void __launch_bounds__(64) finalize_kernel(Group g) {
-  __shared__ double a[kNAcc];
   const int si = find_sys(g, blockIdx.x);
-  const SysDesc& s = g.sys[si];
-  const int p = blockIdx.x - g.block0[si];
-  const int ns = s.nmax < 0 ? A_SHP_BETA : A_SHP_C + (s.nmax + 1) * (s.nmax + 2) / 2;
-  const double* acc = s.acc + (size_t)p * s.tiles * kNAcc;
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    double v = 0.0;
-#pragma unroll 8
-    for (int t = 0; t < s.tiles; ++t) v += acc[t * kNAcc + q];
-    a[q] = v;
-  }
-  __syncthreads();
-  const PConst& c = s.pc[p];
-  if (threadIdx.x == 0 && c.fl_i >= 0) {
-    // the floored sub-pixel: g = sbar d(source light)/d(beta) there (FP64), contracted with
-    // the prologue's exact deflection derivatives; shear terms as the main loop forms them
-    const int k = s.k, HW = s.H * s.W;
-    const int pi = c.fl_i / k, pj = c.fl_j / k, sub = (c.fl_i - pi * k) * k + (c.fl_j - pj * k);
-    const int pix = pi * s.W + pj;
-    const double sb = s.sbar[(size_t)p * HW + pix];
-    const float2 bs = s.beta[((size_t)p * k * k + sub) * HW + pix];
-    double gx, gy;
-    source_light_grad(c, s.nmax, bs.x, bs.y, gx, gy);
-    gx *= sb;
-    gy *= sb;
-    a[A_M_ALPHA] += gx * c.fl_a[0] + gy * c.fl_a[1];
-    a[A_M_T] += gx * c.fl_d[0][0] + gy * c.fl_d[0][1];
-    a[A_M_E1] += gx * c.fl_d[1][0] + gy * c.fl_d[1][1];
-    a[A_M_E2] += gx * c.fl_d[2][0] + gy * c.fl_d[2][1];
-    a[A_M_X] -= gx * c.fl_d[3][0] + gy * c.fl_d[3][1];  // d/dx = -d/dx_c
-    a[A_M_Y] -= gx * c.fl_d[4][0] + gy * c.fl_d[4][1];
-    const double x = float(subpix_coord(s.x0, c.fl_j, s.dxs));
-    const double y = float(subpix_coord(s.y0, c.fl_i, s.dxs));
-    a[A_M_G1] += gx * x - gy * y;
-    a[A_M_G2] += gx * y + gy * x;
-  }
-  __syncthreads();
-  // lane 0 maps the sums (to LDS, not to a lane-private array the compiler would spill);
-  // the lanes then check and store the components
-  __shared__ float gr[kMaxParams];
-  // the shapelet coefficients' components (if any) follow the others, one per lane
-  __shared__ int s_j0;
-  if (threadIdx.x == 0) s_j0 = map_gradient(c, a, s.mass, s.shear, s.lens_light, s.nmax, gr);
-  __syncthreads();
-  const int M = s.nmax < 0 ? 0 : (s.nmax + 1) * (s.nmax + 2) / 2;
-  for (int q = threadIdx.x; q < M; q += blockDim.x) gr[s_j0 + q] = shapelet_coef_grad(c, a, q);
-  __syncthreads();
-  const int j = s_j0 + M;
-  int bad = 0;
-  for (int q = threadIdx.x; q < j; q += blockDim.x) bad |= !isfinite(gr[q]);
-  const bool ok = isfinite(s.logl[p]) && !__any(bad);
-  float* out = s.grad + (size_t)p * s.d;
-  for (int q = threadIdx.x; q < j; q += blockDim.x) out[q] = ok ? gr[q] : 0.f;
-  if (threadIdx.x == 0 && !ok) s.logl[p] = -INFINITY;
+  finalize_particle(g.sys[si], blockIdx.x - g.block0[si]);
 }
 
 }  // namespace glens
