@@ -5,9 +5,11 @@
 // is L_ij) and the diagonal is exponentiated. The ELBO loss E_q[log q - log p~(I, z)] is
 // minimised by Adam over x = (mu, v). Each iteration:
 //   draw     one block per sample s: eps_s ~ N(0, I) (Philox, counter (s, j, k, tag)),
-//            z_s = mu + L eps_s, rounded to FP32 for the likelihood pipeline;
+//            z_s = mu + L eps_s, rounded to FP32 for the likelihood pipeline, and the
+//            pipeline's decode of it (prologue) in the same kernel;
 //   pipeline log L and d log L / d theta at g(z_s) for every sample in one batched launch;
-//   grad     one block per sample: f_s = -log p~(z_s | I) and grad f_s (prior, bijector);
+//   grad     one block per sample: the pipeline's finalize, then f_s = -log p~(z_s | I) and
+//            grad f_s (prior, bijector) in the same kernel;
 //   reduce   one block per chunk of kViChunk samples (staged in LDS): per entry of x the
 //            chunk's sum (in sample order, FP64) of (grad f)_i or (grad f)_i eps_j over its
 //            samples with a finite objective, and the chunk's sum of f and sample count;
@@ -30,6 +32,7 @@
 #include "glens_fit.h"
 #include "glens_fit_device.h"
 #include "glens_host.h"
+#include "glens_particle.h"
 
 namespace glens {
 
@@ -101,14 +104,18 @@ __device__ __forceinline__ void draw_sample(const double* mu, const double* v, i
   }
 }
 
-__global__ void __launch_bounds__(kViThreads) vi_draw_kernel(ViArgs a) {
+// This iteration's draw of sample s = blockIdx.x, then the pipeline's decode of it
+// (prologue): one launch instead of two.
+__global__ void __launch_bounds__(kViThreads) vi_draw_decode_kernel(SysDesc s, ViArgs a) {
   __shared__ double s_eps[kMaxParams];
   draw_sample(a.x, a.x + a.d, a.d, blockIdx.x, a.k, kViDrawTag, a.seed_lo, a.seed_hi, s_eps,
               a.eps, a.z32, nullptr);
+  __syncthreads();  // this sample's z is written
+  prologue_particle(s, blockIdx.x);
 }
 
 // f = -log p~(z | I) and its gradient for one sample (terms summed in parameter order).
-__global__ void __launch_bounds__(kViThreads) vi_grad_kernel(ViArgs a) {
+__device__ __forceinline__ void sample_objective(const ViArgs& a) {
   __shared__ double s_t[kMaxParams];
   __shared__ int s_bad;
   const int c = blockIdx.x;
@@ -129,6 +136,14 @@ __global__ void __launch_bounds__(kViThreads) vi_grad_kernel(ViArgs a) {
     s_bad = bad_any || !isfinite(lp);
     a.f[c] = s_bad ? NAN : -lp;
   }
+}
+
+// The pipeline's finalize (log L and its gradient) for sample blockIdx.x, then f and its
+// gradient: one launch instead of two.
+__global__ void __launch_bounds__(kViThreads) vi_finalize_objective_kernel(SysDesc s, ViArgs a) {
+  finalize_particle(s, blockIdx.x);
+  __syncthreads();  // this sample's log L and gradient are written
+  sample_objective(a);
 }
 
 // Per-chunk sums of the gradient estimate's terms (one block per kViChunk samples).
@@ -272,8 +287,6 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
   a.logl = m->ws.logl;
   a.grad = m->ws.grad;
   a.theta = m->ws.theta;
-  hipLaunchKernelGGL(vi_draw_kernel, dim3(v->n), dim3(kViThreads), 0, st, a);
-  if ((rc = vi_check_launch())) return rc;
   Group g;
   std::memset(&g, 0, sizeof(g));
   g.nsys = 1;
@@ -284,8 +297,13 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
   g.sys[0].theta_out = m->ws.theta;
   g.sys[0].logl = m->ws.logl;
   g.sys[0].grad = m->ws.grad;
-  if ((rc = run_group(g, subpix_key(c), c.K, 2, st))) return rc;
-  hipLaunchKernelGGL(vi_grad_kernel, dim3(v->n), dim3(kViThreads), 0, st, a);
+  g.sys[0].mode = 2;
+  // draw + decode, the pipeline without its first and last stages, finalize + objective
+  hipLaunchKernelGGL(vi_draw_decode_kernel, dim3(v->n), dim3(kViThreads), 0, st, g.sys[0], a);
+  if ((rc = vi_check_launch())) return rc;
+  if ((rc = run_group(g, subpix_key(c), c.K, 2, st, nullptr, false, false))) return rc;
+  hipLaunchKernelGGL(vi_finalize_objective_kernel, dim3(v->n), dim3(kViThreads), 0, st,
+                     g.sys[0], a);
   if ((rc = vi_check_launch())) return rc;
   const int nx = v->d + v->nc, chunks = (v->n + kViChunk - 1) / kViChunk;
   hipLaunchKernelGGL(vi_reduce_kernel, dim3(chunks), dim3(256), 0, st, a);
