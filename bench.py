@@ -394,26 +394,36 @@ def serial_stream(G, stream, K, arrivals):
 
 
 def serving_poisson_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16,
-                          pilot=50):
+                          pilot=50, rate=None, side="both"):
     """A long stream at stable load: the plain loop's service rate from its first `pilot`
-    systems, then both the server and the plain loop under the same Poisson arrivals at 0.8 x
-    that rate (no burst runs)."""
+    systems (or the given arrival rate), then the server and / or the plain loop under the
+    same Poisson arrivals at 0.8 x that rate (no burst runs). side: "both", "served" or
+    "serial" (a stream too long for one run is measured one side per run, under the same
+    arrival times)."""
     import paper_2202_07663_amd as G
     stream = make_stream(n_systems, seed, G)
-    pil_span, _, _ = serial_stream(G, stream[:pilot], K, np.zeros(pilot))
-    lam = 0.8 * pilot / pil_span
+    if rate is None:
+        pil_span, _, _ = serial_stream(G, stream[:pilot], K, np.zeros(pilot))
+        lam = 0.8 * pilot / pil_span
+    else:
+        lam, pilot = float(rate), 0
     arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / lam, len(stream)))
-    span, lat, _, st = serve_stream(G, stream, K, arr, steps_per_tick, max_systems)
-    ser_span, ser_lat, _ = serial_stream(G, stream, K, arr)
     q = lambda x, p: round(float(np.percentile(x, p)), 4)  # noqa: E731
-    return {"stream": "mixed (40-100 px, P 512-4096), Poisson arrivals", "systems": len(stream),
-            "K": K, "poisson_rate_per_s": round(lam, 4), "pilot_systems": pilot,
-            "makespan_s_served": round(span, 2), "makespan_s_serial": round(ser_span, 2),
-            "fits_per_hour_served": round(3600 * len(stream) / span, 1),
-            "fits_per_hour_serial": round(3600 * len(stream) / ser_span, 1),
-            "p50_latency_s": q(lat, 50), "p99_latency_s": q(lat, 99),
-            "p50_latency_serial_s": q(ser_lat, 50), "p99_latency_serial_s": q(ser_lat, 99),
-            "hbm_peak_bytes": int(st["hbm_peak"])}
+    out = {"stream": "mixed (40-100 px, P 512-4096), Poisson arrivals", "systems": len(stream),
+           "K": K, "poisson_rate_per_s": round(lam, 4), "pilot_systems": pilot, "side": side}
+    if side in ("both", "served"):
+        span, lat, _, st = serve_stream(G, stream, K, arr, steps_per_tick, max_systems)
+        out.update({"makespan_s_served": round(span, 2),
+                    "fits_per_hour_served": round(3600 * len(stream) / span, 1),
+                    "p50_latency_s": q(lat, 50), "p99_latency_s": q(lat, 99),
+                    "hbm_peak_bytes": int(st["hbm_peak"])})
+    if side in ("both", "serial"):
+        ser_span, ser_lat, _ = serial_stream(G, stream, K, arr)
+        out.update({"makespan_s_serial": round(ser_span, 2),
+                    "fits_per_hour_serial": round(3600 * len(stream) / ser_span, 1),
+                    "p50_latency_serial_s": q(ser_lat, 50),
+                    "p99_latency_serial_s": q(ser_lat, 99)})
+    return out
 
 
 def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small=False,
@@ -597,6 +607,11 @@ def main():
     ap.add_argument("--c4-only", action="store_true",
                     help="run only the whole fit of the 60x60 EPL + shapelet system (MAP, VI, "
                          "HMC) and print its JSON")
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="with --serve-poisson-only: Poisson arrival rate (systems/s) instead of "
+                         "0.8 x the plain loop's rate measured on a pilot")
+    ap.add_argument("--serve-side", choices=["both", "served", "serial"], default="both",
+                    help="with --serve-poisson-only: which side to run")
     ap.add_argument("--serve-only", choices=["mixed", "small", "tiny"],
                     help="run only the served-against-plain-loop measurement of one stream")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -634,7 +649,8 @@ def main():
         print(json.dumps(_finite({"serving_" + args.serve_only: r}), allow_nan=False), flush=True)
         return
     if args.serve_poisson_only:
-        r = serving_poisson_bench(args.serve_systems, args.serve_steps)
+        r = serving_poisson_bench(args.serve_systems, args.serve_steps, rate=args.serve_rate,
+                                  side=args.serve_side)
         print(json.dumps(_finite({"serving_poisson": r}), allow_nan=False), flush=True)
         return
 

@@ -93,6 +93,29 @@ def test_epl60_grad_4096_sampled(glens, epl60_case):
     _say("epl60 grad logl err", e1, "grad err", e2)
 
 
+def test_largest_system_4096_sampled(glens):
+    """The largest system of the serving stream (100 x 100 px, k = 2, EPL + shear, Sersic lens
+    light, Sersic + shapelets n_max 8: d = 68, 160 000 sub-pixels per vector) in a 4096-vector
+    launch, the largest per-vector work the library takes at the benchmark's batch size: log L
+    and gradient of a sample of the vectors against the oracle."""
+    spec = synth.spec_custom(100, 2, True, True, 8, K=21)
+    truth = synth.draw_truth(spec, 11)
+    om = oracle_model(spec)
+    obs = synth.add_noise(oracle.simulate(om, truth[None, :].astype(np.float64))[0], 11,
+                          spec.sigma_bkg, spec.t_exp)
+    theta = synth.draw_particles(spec, truth, 4096, seed=5)
+    _say("case n100 d68 grad P=4096")
+    m = glens.Model.from_spec(spec, obs)
+    assert m.d == 68
+    ll, g = _run(m, theta)
+    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g))
+    idx = np.r_[0, 1, 700, 2047, 2048, 3333, 4094, 4095]
+    ll_ref, g_ref = oracle.loglik_grad(om, theta[idx].astype(np.float64), obs)
+    e1 = assert_logl_close(ll[idx], ll_ref)
+    e2 = assert_grad_close(g[idx], g_ref, names=spec.names)
+    _say("n100 logl err", e1, "grad err", e2)
+
+
 def test_epl60_simulate_image(glens, epl60_case):
     spec, obs, theta = epl60_case
     m = glens.Model.from_spec(spec, obs)
