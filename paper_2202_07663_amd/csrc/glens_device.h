@@ -527,20 +527,16 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs,
     // (Knuth, TAOCP vol. 2, sec. 4.6.4): b_n = c_n + 2 Re(y) b_(n+1) - |y|^2 b_(n+2) from the
     // top down to n = 0, and the sum is b_0 - Re(y) b_1 + i Im(y) b_1. That is two real FMAs
     // per term where complex Horner takes four. |y| = |eps| < 1, so rounding errors made
-    // early are damped as the recurrence runs down. Terms are taken four per trip;
-    // coefficients past the series length are zero, so rounding the length up to a multiple
-    // of four is exact.
+    // early are damped as the recurrence runs down. The loop runs the particle's own series
+    // length (the same for every lane of the tile, so its control is scalar).
     const double yr = -Xr, yi = -Xi;
     const double r2 = 2.0 * yr, yy = fma(yr, yr, yi * yi);
     double b1 = 0.0, b2 = 0.0;  // b_(n+1), b_(n+2)
-    const int nt4 = (c.nterms + 3) & ~3;
-    for (int n0 = nt4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const double b0 = fma(r2, b1, fma(-yy, b2, cs[n0 + q]));
-        b2 = b1;
-        b1 = b0;
-      }
+#pragma unroll 4
+    for (int n = c.nterms - 1; n >= 0; --n) {
+      const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
+      b2 = b1;
+      b1 = b0;
     }
     Sr = fma(-yr, b2, b1);
     Si = yi * b2;
@@ -600,31 +596,25 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   // dS/dy
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
   const bool sx_series = c.epsabs < kSxClosedMin;
-  const int nd4 = (c.nterms_d + 3) & ~3;
   float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
   if (sx_series) {
-    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const int n = n0 + q;
-        const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
-        d2 = d1;
-        d1 = d0;
-        if (MASS == 1) {
-          const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
-          t2 = t1;
-          t1 = t0;
-        }
-      }
-    }
-  } else if (MASS == 1) {
-    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n0 + q]));
+#pragma unroll 4
+    for (int n = c.nterms_d - 1; n >= 0; --n) {
+      const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
+      d2 = d1;
+      d1 = d0;
+      if (MASS == 1) {
+        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
         t2 = t1;
         t1 = t0;
       }
+    }
+  } else if (MASS == 1) {
+#pragma unroll 4
+    for (int n = c.nterms_d - 1; n >= 0; --n) {
+      const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+      t2 = t1;
+      t1 = t0;
     }
   }
   // S = alpha conj(w) / (A |w|^2)
