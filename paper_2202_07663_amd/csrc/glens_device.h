@@ -503,8 +503,7 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs,
   const double zr = x - c.xc, zi = y - c.yc;
   const double e1 = c.e1, e2 = c.e2;
   const double wr = zr - e1 * zr - e2 * zi, wi = zi - e2 * zr + e1 * zi;
-  double w2 = wr * wr + wi * wi;
-  w2 = w2 < c.w2floor ? c.w2floor : w2;
+  const double w2 = fmax(wr * wr + wi * wi, c.w2floor);
   const double inv_w2 = rcp_f64(w2);
   const double u2r = (wr * wr - wi * wi) * inv_w2, u2i = 2.0 * wr * wi * inv_w2;
   const double Xr = e1 * u2r + e2 * u2i, Xi = e1 * u2i - e2 * u2r;
@@ -527,16 +526,16 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs,
     // (Knuth, TAOCP vol. 2, sec. 4.6.4): b_n = c_n + 2 Re(y) b_(n+1) - |y|^2 b_(n+2) from the
     // top down to n = 0, and the sum is b_0 - Re(y) b_1 + i Im(y) b_1. That is two real FMAs
     // per term where complex Horner takes four. |y| = |eps| < 1, so rounding errors made
-    // early are damped as the recurrence runs down. The loop runs the particle's own series
-    // length (the same for every lane of the tile, so its control is scalar).
+    // early are damped as the recurrence runs down. Terms are taken two per trip (so that the
+    // two carried values need no register moves); coefficients past the series length are
+    // zero, so rounding the length up to an even number is exact.
     const double yr = -Xr, yi = -Xi;
     const double r2 = 2.0 * yr, yy = fma(yr, yr, yi * yi);
     double b1 = 0.0, b2 = 0.0;  // b_(n+1), b_(n+2)
-#pragma unroll 4
-    for (int n = c.nterms - 1; n >= 0; --n) {
-      const double b0 = fma(r2, b1, fma(-yy, b2, cs[n]));
-      b2 = b1;
-      b1 = b0;
+    const int nt2 = (c.nterms + 1) & ~1;
+    for (int n0 = nt2 - 2; n0 >= 0; n0 -= 2) {  // leaves b_n0 in b1 and b_(n0+1) in b2
+      b2 = fma(r2, b1, fma(-yy, b2, cs[n0 + 1]));
+      b1 = fma(r2, b2, fma(-yy, b1, cs[n0]));
     }
     Sr = fma(-yr, b2, b1);
     Si = yi * b2;
@@ -596,25 +595,34 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   // dS/dy
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
   const bool sx_series = c.epsabs < kSxClosedMin;
+  // four terms per trip, the length rounded up to a multiple of four (the padding
+  // coefficients are zero): the LDS reads of a trip go out together, which at this kernel's
+  // three waves per SIMD was measured faster than two terms per trip
+  const int nd4 = (c.nterms_d + 3) & ~3;
   float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
   if (sx_series) {
-#pragma unroll 4
-    for (int n = c.nterms_d - 1; n >= 0; --n) {
-      const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
-      d2 = d1;
-      d1 = d0;
-      if (MASS == 1) {
-        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
-        t2 = t1;
-        t1 = t0;
+    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const int n = n0 + q;
+        const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
+        d2 = d1;
+        d1 = d0;
+        if (MASS == 1) {
+          const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
+          t2 = t1;
+          t1 = t0;
+        }
       }
     }
   } else if (MASS == 1) {
-#pragma unroll 4
-    for (int n = c.nterms_d - 1; n >= 0; --n) {
-      const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
-      t2 = t1;
-      t1 = t0;
+    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n0 + q]));
+        t2 = t1;
+        t1 = t0;
+      }
     }
   }
   // S = alpha conj(w) / (A |w|^2)

@@ -35,11 +35,9 @@ __global__ void __launch_bounds__(64) prologue_kernel(Group g) {
 // ------------------------------------------------------------------------------------------
 // sub-pixel forward: lanes own pixels, loop over the k x k sub-pixels
 // ------------------------------------------------------------------------------------------
-// Copies the particle's series coefficients to LDS (read uniformly by every lane).
-__device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float* s_nc,
-                                             float* s_dc) {
+// Copies the particle's derivative-series coefficients to LDS (read uniformly by every lane).
+__device__ __forceinline__ void stage_series(const PConst& c, float* s_nc, float* s_dc) {
   for (int n = threadIdx.x; n < kMaxTerms; n += blockDim.x) {
-    s_c[n] = c.c[n];
     s_nc[n] = c.nc[n];
     s_dc[n] = c.dc[n];
   }
@@ -47,11 +45,11 @@ __device__ __forceinline__ void stage_series(const PConst& c, double* s_c, float
 }
 
 template <int MASS, int LL, int NMAX>
-__device__ __forceinline__ float surface_brightness(const PConst& c, const double* s_c,
+__device__ __forceinline__ float surface_brightness(const PConst& c, const double* cs,
                                                     const double* s_pw, double x, double y,
                                                     bool at_floor, const float* shp,
                                                     float2& sd) {
-  ray_trace<MASS>(c, s_c, s_pw, x, y, at_floor, sd.x, sd.y);
+  ray_trace<MASS>(c, cs, s_pw, x, y, at_floor, sd.x, sd.y);
   float v = sersic_fwd(c.src, sd.x, sd.y);
   if (NMAX >= 0) v += shapelet_fwd<(NMAX < 0 ? 0 : NMAX)>(c, sd.x, sd.y, shp);
   if (LL) v += sersic_fwd(c.lens, float(x - c.lxs), float(y - c.lys));
@@ -65,7 +63,7 @@ __device__ __forceinline__ float surface_brightness(const PConst& c, const doubl
 template <int MASS, int LL, int NMAX>
 // beta (or null): where beta - x_s of each sub-pixel is kept for the adjoint, [k^2][H][W].
 __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* __restrict__ c,
-                                               const double* s_c, const double* s_pw,
+                                               const double* cs, const double* s_pw,
                                                float* __restrict__ out,
                                                float2* __restrict__ beta, int p0, int p1) {
   const int W = s.W, k = s.k;
@@ -89,7 +87,7 @@ __device__ __forceinline__ void forward_pixels(const SysDesc& s, const PConst* _
         // the SIE's floored sub-pixel takes the prologue's frozen-radius deflection
         const bool at_floor = MASS == 0 && i * k + a == c->fl_i && j * k + b == c->fl_j;
         float2 sd;
-        sum += surface_brightness<MASS, LL, NMAX>(*c, s_c, s_pw, x, y, at_floor, shp, sd);
+        sum += surface_brightness<MASS, LL, NMAX>(*c, cs, s_pw, x, y, at_floor, shp, sd);
         if (beta) {  // streamed past the caches: read once, by the adjoint, much later
           float* bp = reinterpret_cast<float*>(beta + (a * k + b) * (s.H * W) + pix);
           __builtin_nontemporal_store(sd.x, bp);
@@ -108,16 +106,17 @@ __global__ void __launch_bounds__(kSubThreads) subpix_fwd_kernel(Group g) {
   const int lb = blockIdx.x - g.block0[si];
   const int part = lb / s.ftiles, tile = lb - part * s.ftiles;
   const PConst& c = s.pc[part];
-  __shared__ double s_c[kMaxTerms];
-  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
+  // the power tables in LDS (lanes read entries of their own); the value series' coefficients
+  // stay in the particle's constants, read through the scalar cache: uniform over the
+  // workgroup, they enter the series' FMAs as scalar operands
   __shared__ double s_pw[kPowExp + kPowSeg * 8];
   for (int i = threadIdx.x; i < kPowExp + kPowSeg * 8; i += blockDim.x) s_pw[i] = c.pw[i];
-  stage_series(c, s_c, s_nc, s_dc);  // its barrier also covers the power tables
+  __syncthreads();
   const int HW = s.H * s.W;
   const int p0 = tile * s.fpix_per_tile;
   const int p1 = min(HW, p0 + s.fpix_per_tile);
   float2* beta = s.mode == 2 && s.beta ? s.beta + (size_t)part * s.k * s.k * HW : nullptr;
-  forward_pixels<MASS, LL, NMAX>(s, &c, s_c, s_pw, s.m0 + (size_t)part * HW, beta, p0, p1);
+  forward_pixels<MASS, LL, NMAX>(s, &c, c.c, s_pw, s.m0 + (size_t)part * HW, beta, p0, p1);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -785,9 +784,8 @@ subpix_adj_kernel(Group g) {
   const int lb = blockIdx.x - g.block0[si];
   const int part = lb / s.tiles, tile = lb - part * s.tiles;
   const PConst& c = s.pc[part];
-  __shared__ double s_c[kMaxTerms];
   __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
-  stage_series(c, s_c, s_nc, s_dc);
+  stage_series(c, s_nc, s_dc);
   // beta - x_s from the forward pass (kept there for gradient calls)
   const float2* beta = s.beta + (size_t)part * s.k * s.k * s.H * s.W;
   const int HW = s.H * s.W, W = s.W, k = s.k;
