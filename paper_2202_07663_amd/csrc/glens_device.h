@@ -597,25 +597,12 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   const bool sx_series = c.epsabs < kSxClosedMin;
   // four terms per trip, the length rounded up to a multiple of four (the padding
   // coefficients are zero): the LDS reads of a trip go out together, which at this kernel's
-  // three waves per SIMD was measured faster than two terms per trip
+  // three waves per SIMD was measured faster than two terms per trip. dS/dt (EPL) here, dS/dy
+  // (small |eps| only) below in a loop of its own, so that the common path carries no state
+  // of the other.
   const int nd4 = (c.nterms_d + 3) & ~3;
-  float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
-  if (sx_series) {
-    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const int n = n0 + q;
-        const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n]));
-        d2 = d1;
-        d1 = d0;
-        if (MASS == 1) {
-          const float t0 = fmaf(r2, t1, fmaf(-yy, t2, dcs[n]));
-          t2 = t1;
-          t1 = t0;
-        }
-      }
-    }
-  } else if (MASS == 1) {
+  float t1 = 0.f, t2 = 0.f;
+  if (MASS == 1) {
     for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
 #pragma unroll
       for (int q = 3; q >= 0; --q) {
@@ -630,6 +617,15 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   const float Sr = (ar * wr + ai * wi) * r;
   const float Si = (ai * wr - ar * wi) * r;
   if (sx_series) {
+    float d1 = 0.f, d2 = 0.f;
+    for (int n0 = nd4 - 4; n0 >= 0; n0 -= 4) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const float d0 = fmaf(r2, d1, fmaf(-yy, d2, ncs[n0 + q]));
+        d2 = d1;
+        d1 = d0;
+      }
+    }
     const Cx SX = {-fmaf(-yr, d2, d1), -yi * d2};  // dS/dX = -dS/dy
     m.XSX = cmul(m.X, SX);
     m.U2SX = cmul(m.u2, SX);
@@ -702,7 +698,7 @@ GL_HD void mass_adjoint(const PConst& c, const MassState& m, float x, float y, C
 GL_HD float sersic_fwd(const LightC& L, float dx, float dy) {
   // R^2 = dx (qa dx + qb dy) + qc dy^2
   float q = fmaf(dx, fmaf(L.qb, dy, L.qa * dx), L.qc * dy * dy);
-  q = q < kR2Floor ? kR2Floor : q;
+  q = q < kR2Floor ? kR2Floor : q;  // a select, not fmaxf: a NaN offset stays NaN
   // rho = (R / R_eff)^(1/n) = 2^(log2(R^2) / (2n) - log2(R_eff) / n);  I = I0 e^(b_n (1 - rho))
   const float rho = exp2_f32(fmaf(log2_f32(q), L.inv2n, -L.l2re_n));
   return L.i0 * exp2_f32(fmaf(-L.bnl, rho, L.bnl));
