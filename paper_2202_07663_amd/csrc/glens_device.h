@@ -567,8 +567,9 @@ GL_HD void ray_trace(const PConst& c, const double* __restrict__ cs,
 // |w|^2 is kept at or above the floor so that every quantity stays finite; the particle's
 // floored sub-pixel itself (c.fl_*) takes its mass terms from the prologue's exact
 // derivatives instead (the caller passes a zero weight here).
-// ncs / dcs: the particle's c.nc / c.dc (staged in LDS).
-template <int MASS>
+// ncs / dcs: the particle's c.nc / c.dc (staged in LDS). SXS = false: the caller has checked
+// that |eps| >= kSxClosedMin, so dS/dX takes the closed form without a test.
+template <int MASS, bool SXS = true>
 __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* __restrict__ ncs,
                                                   const float* __restrict__ dcs, double x,
                                                   double y, float sdx, float sdy, MassState& m) {
@@ -594,7 +595,7 @@ __device__ __forceinline__ void mass_jacobian_f32(const PConst& c, const float* 
   // series by synthetic division at y = -X (ray_trace): dS/dt (EPL) and, for small |eps|,
   // dS/dy
   const float yr = -Xr, yi = -Xi, r2 = 2.0f * yr, yy = yr * yr + yi * yi;
-  const bool sx_series = c.epsabs < kSxClosedMin;
+  const bool sx_series = SXS && c.epsabs < kSxClosedMin;
   // four terms per trip, the length rounded up to a multiple of four (the padding
   // coefficients are zero): the LDS reads of a trip go out together, which at this kernel's
   // three waves per SIMD was measured faster than two terms per trip. dS/dt (EPL) here, dS/dy

@@ -774,36 +774,15 @@ __device__ __forceinline__ void wave_sums(const float* acc, double* out) {
   }
 }
 
-template <int MASS, int LL, int NMAX>
-__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3)))
-subpix_adj_kernel(Group g) {
-  constexpr int NS = n_slots<NMAX>();
-  __shared__ double red[kSubThreads / 64][NS];
-  const int si = find_sys(g, blockIdx.x);
-  const SysDesc& s = g.sys[si];
-  const int lb = blockIdx.x - g.block0[si];
-  const int part = lb / s.tiles, tile = lb - part * s.tiles;
-  const PConst& c = s.pc[part];
-  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
-  stage_series(c, s_nc, s_dc);
-  // beta - x_s from the forward pass (kept there for gradient calls)
-  const float2* beta = s.beta + (size_t)part * s.k * s.k * s.H * s.W;
+// The sub-pixels of pixels [p0, p1) of one particle into the per-lane accumulators.
+// GENERAL = false: the particle has no floored sub-pixel and |eps| >= kSxClosedMin.
+template <int MASS, int LL, int NMAX, bool GENERAL>
+__device__ __forceinline__ void adj_pixels(const SysDesc& s, const PConst& c,
+                                           const float* s_nc, const float* s_dc,
+                                           const float* shp, const float2* beta,
+                                           const float* sbar, int p0, int p1, float* acc) {
   const int HW = s.H * s.W, W = s.W, k = s.k;
-  const int p0 = tile * s.pix_per_tile;
-  const int p1 = min(HW, p0 + s.pix_per_tile);
-  const float* sbar = s.sbar + (size_t)part * HW;
-  float acc[NS];
-#pragma unroll
-  for (int q = 0; q < NS; ++q) acc[q] = 0.f;
-  // shapelet coefficients in vector registers (as in the forward pass): their sums then start
-  // from a register operand instead of a copy of a scalar one
-  constexpr int M = NMAX < 0 ? 1 : (NMAX + 1) * (NMAX + 2) / 2;
-  float shp[M];
-#pragma unroll
-  for (int q = 0; q < M; ++q) {
-    shp[q] = NMAX < 0 ? 0.f : c.shp[q];
-    asm("" : "+v"(shp[q]));
-  }
+  const int fl_i = c.fl_i, fl_j = c.fl_j;
   for (int pix = p0 + threadIdx.x; pix < p1; pix += blockDim.x) {
     const int i = pix / W, j = pix - i * W;
     const float sb = sbar[pix];
@@ -813,8 +792,8 @@ subpix_adj_kernel(Group g) {
         const double x = subpix_coord(s.x0, j * k + b, s.dxs);
         MassState m;
         const float* bp = reinterpret_cast<const float*>(beta + (a * k + b) * HW + pix);
-        mass_jacobian_f32<MASS>(c, s_nc, s_dc, x, y, __builtin_nontemporal_load(bp),
-                                __builtin_nontemporal_load(bp + 1), m);
+        mass_jacobian_f32<MASS, GENERAL>(c, s_nc, s_dc, x, y, __builtin_nontemporal_load(bp),
+                                         __builtin_nontemporal_load(bp + 1), m);
         // gx, gy: sb d(source light)/d(beta)
         float gx, gy;
         sersic_adj(c.src, m.sdx, m.sdy, sb, acc + A_SRC, gx, gy);
@@ -834,12 +813,50 @@ subpix_adj_kernel(Group g) {
         }
         // the floored sub-pixel's mass terms are added by finalize from the prologue's
         // exact derivatives
-        const bool at_floor = i * k + a == c.fl_i && j * k + b == c.fl_j;
+        const bool at_floor = GENERAL && i * k + a == fl_i && j * k + b == fl_j;
         mass_adjoint<MASS>(c, m, float(x), float(y),
                            at_floor ? Cx{0.f, 0.f} : Cx{gx, gy}, acc);
       }
     }
   }
+}
+
+template <int MASS, int LL, int NMAX>
+__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3)))
+subpix_adj_kernel(Group g) {
+  constexpr int NS = n_slots<NMAX>();
+  __shared__ double red[kSubThreads / 64][NS];
+  const int si = find_sys(g, blockIdx.x);
+  const SysDesc& s = g.sys[si];
+  const int lb = blockIdx.x - g.block0[si];
+  const int part = lb / s.tiles, tile = lb - part * s.tiles;
+  const PConst& c = s.pc[part];
+  __shared__ float s_nc[kMaxTerms], s_dc[kMaxTerms];
+  stage_series(c, s_nc, s_dc);
+  // beta - x_s from the forward pass (kept there for gradient calls)
+  const float2* beta = s.beta + (size_t)part * s.k * s.k * s.H * s.W;
+  const int HW = s.H * s.W;
+  const int p0 = tile * s.pix_per_tile;
+  const int p1 = min(HW, p0 + s.pix_per_tile);
+  const float* sbar = s.sbar + (size_t)part * HW;
+  float acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.f;
+  // shapelet coefficients in vector registers (as in the forward pass): their sums then start
+  // from a register operand instead of a copy of a scalar one
+  constexpr int M = NMAX < 0 ? 1 : (NMAX + 1) * (NMAX + 2) / 2;
+  float shp[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    shp[q] = NMAX < 0 ? 0.f : c.shp[q];
+    asm("" : "+v"(shp[q]));
+  }
+  // the common case (no floored sub-pixel, |eps| >= kSxClosedMin) runs a loop without those
+  // tests
+  if (c.fl_i < 0 && !(c.epsabs < kSxClosedMin))
+    adj_pixels<MASS, LL, NMAX, false>(s, c, s_nc, s_dc, shp, beta, sbar, p0, p1, acc);
+  else
+    adj_pixels<MASS, LL, NMAX, true>(s, c, s_nc, s_dc, shp, beta, sbar, p0, p1, acc);
   // FP64 sums: across the wave, then across the waves of the block
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   wave_sums<NS>(acc, red[wave]);
