@@ -177,7 +177,7 @@ def workload():
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
                    chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100,
                    adapt_length=True, vi_lr=1e-3, vi_warmup=500, vi_init_sd=1e-3,
-                   map_result=None):
+                   map_result=None, vi_lr_final=0.0, adapt_mass=False):
     """map_result: (fit result, seconds) of a MAP stage already run with these settings (the
     stage is then not run again; its time is reported as measured there)."""
     import torch
@@ -196,14 +196,15 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
         t1 = time.perf_counter()
         t0 = t1 - dt_map
     vi = G.VI(model, n_vi, k_vi, priors, r["z_best"].astype(np.float64), lr_max=vi_lr,
-              lr_warmup=vi_warmup, init_sd=vi_init_sd, seed=seed + 1)
+              lr_warmup=vi_warmup, init_sd=vi_init_sd, seed=seed + 1, lr_final=vi_lr_final)
     vi.step()
     got = vi.get()
     z0 = vi.sample(chains, seed=seed + 2)
     chol = got["chol"].cpu().numpy()
     t2 = time.perf_counter()
     h = G.HMC(model, chains, L, n_burn, n_samples, priors, step_size=0.3, seed=seed + 3,
-              z0=z0, mass_chol=chol, adapt_length=adapt_length, max_leapfrog=max_leapfrog)
+              z0=z0, mass_chol=chol, adapt_length=adapt_length, max_leapfrog=max_leapfrog,
+              adapt_mass=adapt_mass)
     h.run()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -219,8 +220,10 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     grad_evals = n_map * k_map + n_vi * k_vi + round(chains * (n_burn + n_samples) *
                                                      info["mean_leapfrog"])
     return {
-        "config": {"map": [n_map, k_map], "vi": [n_vi, k_vi, vi_lr, vi_init_sd],
-                   "hmc": {"chains": chains, "L": L, "burn": n_burn, "samples": n_samples}},
+        "config": {"map": [n_map, k_map],
+                   "vi": [n_vi, k_vi, vi_lr, vi_init_sd] + ([vi_lr_final] if vi_lr_final else []),
+                   "hmc": {"chains": chains, "L": L, "burn": n_burn, "samples": n_samples,
+                           **({"adapt_mass": True} if adapt_mass else {})}},
         "seconds": {"map": round(t1 - t0, 3), "vi": round(t2 - t1, 3), "hmc": round(t3 - t2, 3),
                     "total": round(t3 - t0, 3)},
         "grad_evals": grad_evals,
@@ -229,6 +232,7 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
                                                         info["mean_leapfrog"]), 2),
         "hmc_trajectory_length": round(info["trajectory_length"], 4),
         "hmc_mean_leapfrog": round(info["mean_leapfrog"], 2),
+        "hmc_mass_updates": info["mass_updates"],
         "map_chi2nu": round(r["chi2nu"], 4),
         "hmc_accept": round(info["accept_mean"], 4),
         "hmc_step_size": info["step_size"],
@@ -465,8 +469,9 @@ def serving_bench(n_systems, K, seed=0, steps_per_tick=10, max_systems=16, small
 
 def c4_bench(G, spec):
     """The whole fit of the 60x60 EPL + shapelet system (stored observation, seed 0): 4096
-    starts, VI 1000 x 1000, HMC 64 chains x (250 + 750) trajectories x 10 leapfrog steps; then
-    the same MAP point with a longer surrogate fit and longer chains."""
+    starts, VI 1000 x 1000, HMC 64 chains x (250 + 750) trajectories x 10 leapfrog steps, as
+    the paper runs it and with the mass matrix re-estimated during burn-in; then the same MAP
+    point with a longer surrogate fit whose rate decays, and longer chains."""
     import torch
     import synth
     # At this signal-to-noise (sigma_bkg 0.1, t_exp 1000 s) and d = 51 the multi-start Adam
@@ -493,13 +498,18 @@ def c4_bench(G, spec):
                                                n_burn=250, n_samples=750,
                                                adapt_length=False, map_result=map_res))
     print("c4: Table 1 VI and HMC done", file=sys.stderr, flush=True)
+    out["c4_pipeline_adapt_mass"] = dict(workload="epl60_s0", **pipeline_bench(
+        spec, obs0, truth0, n_map=4096, k_map=10000, n_vi=1000, k_vi=1000, chains=64, L=10,
+        n_burn=250, n_samples=750, adapt_length=False, map_result=map_res, adapt_mass=True))
+    print("c4: Table 1 sizes with mass adaptation done", file=sys.stderr, flush=True)
     # the same MAP point with a longer surrogate fit (Table 1's 1000 iterations at 1e-3
     # cannot shrink the surrogate from sd 1e-3 to this posterior's widths of 1e-4 and
-    # below) and longer chains
+    # below; at a constant 3e-3 its mean never settles within those widths, so the rate
+    # decays geometrically to 1e-4) and longer chains
     out["c4_pipeline_long"] = dict(workload="epl60_s0", **pipeline_bench(
-        spec, obs0, truth0, n_map=4096, k_map=10000, n_vi=1000, k_vi=6000, chains=64, L=10,
+        spec, obs0, truth0, n_map=4096, k_map=10000, n_vi=1000, k_vi=10000, chains=64, L=10,
         n_burn=1000, n_samples=1000, adapt_length=False, vi_lr=3e-3, vi_warmup=300,
-        map_result=map_res))
+        vi_lr_final=1e-4, map_result=map_res))
     return out
 
 
@@ -759,6 +769,9 @@ def main():
         sp = synth.spec_paper80()
         out["pipeline"] = dict(workload="paper80_s6", **pipeline_bench(
             sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=1000, chains=50, L=5))
+        out["pipeline_adapt_mass"] = dict(workload="paper80_s6", **pipeline_bench(
+            sp, *stored(sp, 6), n_map=300, k_map=300, n_vi=500, k_vi=1000, chains=50, L=5,
+            adapt_mass=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, obs, theta_np, args.cpu_sample)
     print(json.dumps(_finite(out), allow_nan=False), flush=True)

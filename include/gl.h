@@ -242,7 +242,12 @@ int gl_fit_state_result(gl_fit_state* st, gl_fit_result* out, void* stream);
  * (grad f)_i eps_j for L_ij (i > j), and of L_ii (grad f)_i eps_i - 1 for v_ii. (The paper
  * prints the score-function form of the same gradient; both estimate it without bias.)
  * Adam (beta1, beta2, eps; 0.9, 0.999, 1e-8 if all are 0) then steps x with learning rate
- * lr_max (1 - (1 - min(k, lr_warmup) / lr_warmup)^2) (the paper: 1e-3, warm-up 500).
+ * lr_max (1 - (1 - min(k, lr_warmup) / lr_warmup)^2) (the paper: 1e-3, warm-up 500), then
+ * lr_max, or, with lr_final > 0 (not in the paper), a geometric decay after the warm-up:
+ * lr_max (lr_final / lr_max)^((k - lr_warmup) / (K - 1 - lr_warmup)), which ends at lr_final
+ * on the last iteration (k = K - 1). The decay lets the mean settle in posteriors whose
+ * widths are far below lr_max: Adam moves every coordinate by about the learning rate per
+ * iteration, so a constant rate keeps the mean that far from its optimum.
  * ------------------------------------------------------------------------------------- */
 typedef struct gl_vi_opts {
   int n_samples;          /* n_VI, >= 1 */
@@ -253,6 +258,8 @@ typedef struct gl_vi_opts {
   float init_sd;          /* > 0 */
   uint64_t seed;
   const gl_prior* priors; /* host [d], copied */
+  float lr_final;         /* 0: constant after the warm-up; > 0 (with lr_max > 0): the rate
+                             on the last iteration, reached geometrically */
 } gl_vi_opts;
 
 typedef struct gl_vi gl_vi;
@@ -298,6 +305,16 @@ int gl_vi_set_state(gl_vi* v, const double* x, const double* m, const double* s,
  * ChEES = E[(|z' - E z'|^2 - |z - E z|^2)^2] / 4, whose per-chain term is
  * (|z' - zbar'|^2 - |z - zbar|^2) ((z' - zbar') . M^-1 p') u T (means over chains); T is then
  * fixed at its average with weights m^-0.75. The paper adapts both as in these references.
+ * With adapt_mass (not in the paper, whose M^-1 is the variational covariance throughout),
+ * M^-1 is re-estimated during the same adaptation window, as in Stan's windowed adaptation:
+ * after an initial buffer of floor(0.15 n_adapt) trajectories, three windows of lengths in
+ * the ratio 1 : 2 : 4 fill the trajectories up to a terminal buffer of floor(0.10 n_adapt)
+ * (n_adapt = floor(adapt_frac n_burn); no windows if they would cover fewer than 7
+ * trajectories). At the end of each window M^-1 becomes the sample covariance of the chains'
+ * positions after that window's trajectories (n = chains x window length samples), its
+ * off-diagonal entries scaled by n / (n + 5) (shrinkage towards the diagonal), unless that is
+ * not positive definite; the step-size averaging then restarts with mu = log(10 eps). Each
+ * window end waits for the stream (the estimate is factored on the host).
  * Every chain is one particle of the likelihood pipeline: a leapfrog step is one batched
  * gradient launch over all chains. Random numbers: Philox4x32-10 keyed by `seed`, counter
  * (chain, parameter, trajectory, purpose).
@@ -321,6 +338,7 @@ typedef struct gl_hmc_opts {
                                   GL_MASS_CHOL: its lower Cholesky factor [d][d] row-major
                                   (positive diagonal; entries above it are ignored) */
   const gl_prior* priors;      /* host [d], copied */
+  int adapt_mass;              /* 1: re-estimate M^-1 during adaptation (see above) */
 } gl_hmc_opts;
 
 typedef struct gl_hmc_info {
@@ -329,6 +347,7 @@ typedef struct gl_hmc_info {
   int trajectories;      /* trajectories run so far */
   float trajectory_length; /* T (adapted), or n_leapfrog eps without length adaptation */
   double mean_leapfrog;  /* mean leapfrog steps per trajectory so far */
+  int mass_updates;      /* times M^-1 was replaced by an estimate (adapt_mass) */
 } gl_hmc_info;
 
 typedef struct gl_hmc gl_hmc;
@@ -350,6 +369,10 @@ int gl_hmc_run(gl_hmc* h, int n, void* stream);
 int gl_hmc_samples(gl_hmc* h, float* theta, void* stream);
 /* Step size, mean acceptance and progress (blocking). */
 int gl_hmc_get_info(gl_hmc* h, gl_hmc_info* out, void* stream);
+/* Copy the current lower Cholesky factor C of M^-1 = C C^T (the given one, or the last
+ * estimate of the mass adaptation) to chol: device [d][d] FP32 row-major, zero above the
+ * diagonal. */
+int gl_hmc_get_mass(gl_hmc* h, float* chol, void* stream);
 /* L leapfrog steps of size eps (no momentum draw, no accept, no adaptation) from caller
  * positions z (device [chains][d] FP64) and momenta p (device [chains][d] FP32), writing
  * the end point to z_out (FP64), p_out (FP32) and log p~(z_L | I) to logpost_out (device

@@ -48,14 +48,20 @@ def cholesky_inverse(L):
     return L[tril_index(L.shape[0])]
 
 
-def learning_rate(k, lr_max, warmup):
+def learning_rate(k, lr_max, warmup, lr_final=0.0, K=0):
     """Polynomial schedule of power 2 from 0 to lr_max over `warmup` iterations (the form
     of a polynomial decay from init 0 to end lr_max): lr_max (1 - (1 - k/warmup)^2), then
-    constant."""
-    if warmup <= 0:
+    constant (Sec. 2.4's schedule). With lr_final > 0 (an option of this implementation, not
+    the paper's), the rate after the warm-up falls geometrically from lr_max at k = warmup to
+    lr_final at the last of K iterations, k = K - 1."""
+    if k < warmup:
+        frac = 1.0 - k / warmup
+        return lr_max * (1.0 - frac * frac)
+    span = K - 1 - warmup
+    if lr_final <= 0 or span <= 0:
         return lr_max
-    frac = 1.0 - min(k, warmup) / warmup
-    return lr_max * (1.0 - frac * frac)
+    t = min(1.0, (k - warmup) / span)
+    return lr_max * (lr_final / lr_max) ** t
 
 
 def draws(seed, d, n, k):

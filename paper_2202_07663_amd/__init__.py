@@ -284,17 +284,19 @@ def fit(model: Model, P: int, K: int, priors, lr0=1e-2, lr1=1e-3, seed=0, stream
 class VI:
     """Multivariate normal surrogate of one system's posterior in unconstrained space, fitted
     by the library's kernels (one batched likelihood-gradient launch per iteration).
-    mu0: [d] start of the mean (the paper: the MAP point, e.g. fit(...)["z_best"])."""
+    mu0: [d] start of the mean (the paper: the MAP point, e.g. fit(...)["z_best"]).
+    lr_final: 0 keeps lr_max after the warm-up (the paper); > 0 decays the rate geometrically
+    to lr_final on the last iteration."""
 
     def __init__(self, model: Model, n_samples: int, K: int, priors, mu0, lr_max: float = 1e-3,
                  lr_warmup: int = 500, init_sd: float = 1e-3, seed: int = 0, beta1=0.9,
-                 beta2=0.999, eps=1e-8, stream=None):
+                 beta2=0.999, eps=1e-8, lr_final: float = 0.0, stream=None):
         assert len(priors) == model.d
         self.model, self.n, self.K, self.d = model, n_samples, K, model.d
         self._pa = make_priors(priors)
         o = _lib.ViOpts(n_samples=n_samples, K=K, lr_max=lr_max, lr_warmup=lr_warmup,
                         beta1=beta1, beta2=beta2, eps=eps, init_sd=init_sd, seed=seed,
-                        priors=self._pa)
+                        priors=self._pa, lr_final=lr_final)
         mu = torch.as_tensor(np.asarray(mu0, np.float64)).reshape(model.d).cuda()
         h = ctypes.c_void_p()
         check(lib().gl_vi_create(model._h, ctypes.byref(o), mu.data_ptr(), ctypes.byref(h),
@@ -363,13 +365,14 @@ class HMC:
     z0: optional [chains, d] unconstrained starts (e.g. the fit's best particle plus
     jitter; kept in FP64); inv_mass: optional inverse mass matrix M^-1, the diagonal [d] or the full
     [d, d] (the paper uses the variational posterior covariance of z); mass_chol: instead, the
-    lower Cholesky factor of M^-1 (e.g. VI.get()["chol"])."""
+    lower Cholesky factor of M^-1 (e.g. VI.get()["chol"]). adapt_mass: re-estimate M^-1 from
+    the chains in three windows of the adaptation period (not in the paper)."""
 
     def __init__(self, model: Model, chains: int, n_leapfrog: int, n_burn: int, n_samples: int,
                  priors, step_size: float = 1e-2, target_accept: float = 0.75,
                  adapt_frac: float = 0.8, seed: int = 0, z0: torch.Tensor | None = None,
                  inv_mass=None, mass_chol=None, adapt_length: bool = False,
-                 max_leapfrog: int = 1000, stream=None):
+                 max_leapfrog: int = 1000, adapt_mass: bool = False, stream=None):
         assert len(priors) == model.d
         self.model, self.C = model, chains
         self.n_burn, self.n_samples = n_burn, n_samples
@@ -377,7 +380,8 @@ class HMC:
         o = _lib.HmcOpts(chains=chains, n_leapfrog=n_leapfrog, n_burn=n_burn,
                          n_samples=n_samples, step_size=step_size, target_accept=target_accept,
                          adapt_frac=adapt_frac, seed=seed, priors=self._pa,
-                         adapt_length=int(adapt_length), max_leapfrog=max_leapfrog)
+                         adapt_length=int(adapt_length), max_leapfrog=max_leapfrog,
+                         adapt_mass=int(adapt_mass))
         if inv_mass is not None or mass_chol is not None:
             assert inv_mass is None or mass_chol is None
             im = np.ascontiguousarray(np.asarray(inv_mass if mass_chol is None else mass_chol,
@@ -414,7 +418,13 @@ class HMC:
         check(lib().gl_hmc_get_info(self._h, ctypes.byref(r), _stream_ptr(stream)))
         return {"step_size": r.step_size, "accept_mean": r.accept_mean,
                 "trajectories": r.trajectories, "trajectory_length": r.trajectory_length,
-                "mean_leapfrog": r.mean_leapfrog}
+                "mean_leapfrog": r.mean_leapfrog, "mass_updates": r.mass_updates}
+
+    def mass_chol(self, stream=None) -> torch.Tensor:
+        """[d, d] current lower Cholesky factor of M^-1 (FP32, cuda)."""
+        out = torch.empty((self.model.d, self.model.d), dtype=torch.float32, device="cuda")
+        check(lib().gl_hmc_get_mass(self._h, out.data_ptr(), _stream_ptr(stream)))
+        return out
 
     def leapfrog(self, z: torch.Tensor, p: torch.Tensor, L: int, eps: float, stream=None):
         """L leapfrog steps from (z, p) (no accept): returns z_L (FP64), p_L (FP32) and

@@ -59,13 +59,14 @@ class HmcOpts(ctypes.Structure):
                 ("target_accept", ctypes.c_float), ("adapt_frac", ctypes.c_float),
                 ("seed", ctypes.c_uint64), ("inv_mass", ctypes.POINTER(ctypes.c_float)),
                 ("adapt_length", ctypes.c_int), ("max_leapfrog", ctypes.c_int),
-                ("inv_mass_form", ctypes.c_int), ("priors", ctypes.POINTER(Prior))]
+                ("inv_mass_form", ctypes.c_int), ("priors", ctypes.POINTER(Prior)),
+                ("adapt_mass", ctypes.c_int)]
 
 
 class HmcInfo(ctypes.Structure):
     _fields_ = [("step_size", ctypes.c_float), ("accept_mean", ctypes.c_double),
                 ("trajectories", ctypes.c_int), ("trajectory_length", ctypes.c_float),
-                ("mean_leapfrog", ctypes.c_double)]
+                ("mean_leapfrog", ctypes.c_double), ("mass_updates", ctypes.c_int)]
 
 
 class ViOpts(ctypes.Structure):
@@ -73,7 +74,7 @@ class ViOpts(ctypes.Structure):
                 ("lr_warmup", ctypes.c_int), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("init_sd", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("priors", ctypes.POINTER(Prior))]
+                ("priors", ctypes.POINTER(Prior)), ("lr_final", ctypes.c_float)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -124,6 +125,7 @@ _SIGNATURES = {
     "gl_hmc_run": [_vp, _i, _vp],
     "gl_hmc_samples": [_vp, _vp, _vp],
     "gl_hmc_get_info": [_vp, ctypes.POINTER(HmcInfo), _vp],
+    "gl_hmc_get_mass": [_vp, _vp, _vp],
     "gl_hmc_leapfrog": [_vp, _vp, _vp, _i, ctypes.c_float, _vp, _vp, _vp, _vp],
     "gl_vi_create": [_vp, ctypes.POINTER(ViOpts), _vp, ctypes.POINTER(_vp), _vp],
     "gl_vi_destroy": [_vp],

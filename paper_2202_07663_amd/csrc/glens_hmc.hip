@@ -11,7 +11,11 @@
 // n ~ N(0, I), p^T S p / 2 = |C^T p|^2 / 2 and the drift applies C (C^T p).
 // During the first adapt_frac of burn-in the step size follows Hoffman & Gelman's dual
 // averaging towards target_accept (the paper uses 0.75 over the first 80% of burn-in); it
-// is then fixed at the averaged value. Every chain is one particle of the likelihood launch,
+// is then fixed at the averaged value. With mass adaptation (not in the paper), M^-1 is
+// re-estimated inside the same adaptation window from the chains' positions over three
+// windows of trajectories, each twice as long as the one before, between an initial buffer
+// (15% of the window) and a terminal one (10%), the estimate of each replacing the factor
+// and restarting the step-size averaging. Every chain is one particle of the likelihood launch,
 // so a leapfrog step costs one batched gradient call over all chains; the pipeline's last
 // stage (finalize), the kick and drift and the next step's decode (prologue) run fused in
 // one per-chain kernel, so that a step after the first launches the sub-pixel forward pass,
@@ -70,6 +74,11 @@ struct HmcArgs {
   double* la;          // log T, Adam second moment, update count, averaged log T
   double* zbar;        // [2][d] chain means of the starts and of the proposals
   double* cg;          // [C] ChEES gradient term of each chain
+  // mass adaptation
+  double* mom;         // moments of the current window: [0] count, [1 + i] sum of
+                       // (z - zref)_i, [1 + d + i d + j] sum of (z - zref)_i (z - zref)_j
+  double* zref;        // [d] shift of those sums (chain 0's position at the window start),
+                       // so that they hold deviations of the posterior's width, not of |z|
 };
 
 __device__ __forceinline__ float step_size(const HmcArgs& a) {
@@ -331,6 +340,31 @@ __global__ void hmc_adapt_kernel(HmcArgs a) {
   *a.traj = traj + 1;
 }
 
+// Mass adaptation: clear the window's moments and take chain 0's position as their shift.
+__global__ void __launch_bounds__(256) hmc_window_start_kernel(HmcArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < 1 + a.d + a.d * a.d) a.mom[q] = 0.0;
+  if (q < a.d) a.zref[q] = a.z[q];
+}
+
+// Mass adaptation: add the chains' positions after this trajectory's accept to the window's
+// moments (one lane per entry, chains in order).
+__global__ void __launch_bounds__(256) hmc_moments_kernel(HmcArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.d * a.d) return;
+  const int i = q / a.d, j = q - i * a.d;
+  const double ri = a.zref[i], rj = a.zref[j];
+  double s = 0.0, s1 = 0.0;
+  for (int c = 0; c < a.C; ++c) {
+    const double ei = a.z[size_t(c) * a.d + i] - ri;
+    s += ei * (a.z[size_t(c) * a.d + j] - rj);
+    s1 += ei;
+  }
+  a.mom[1 + a.d + q] += s;
+  if (j == 0) a.mom[1 + i] += s1;
+  if (q == 0) a.mom[0] += a.C;
+}
+
 // Starts drawn from the prior when the caller gives none.
 __global__ void __launch_bounds__(256) hmc_start_kernel(HmcArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -359,6 +393,11 @@ struct gl_hmc {
   long long leapfrogs = 0;  // leapfrog steps run by gl_hmc_run
   float T_fixed = 0.f, eps_fixed = 0.f;  // cached once adaptation has ended
   float T0 = 0.f, eps0 = 0.f;            // the values before the first update
+  // mass adaptation: window k takes the positions after trajectories [win[k], win[k + 1])
+  std::vector<int> win;
+  int mass_updates = 0;
+  float* chol_d = nullptr;
+  float* chol_it_d = nullptr;
   bool pc_ready = false;  // the chains' particle constants are those of their current z
   float* te_host = nullptr;  // pinned: (T, eps) after trajectory j's update, in slot j & 1
   hipEvent_t te_ev[2] = {nullptr, nullptr};  // the copies into each slot
@@ -418,6 +457,51 @@ static std::vector<double> inverse_transpose_lower(const std::vector<double>& l,
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) t[i * d + j] = inv[j * d + i];
   return t;
+}
+
+// Window boundaries of the mass adaptation over n_adapt trajectories: an initial buffer of
+// 15%, three windows in the ratio 1 : 2 : 4, a terminal buffer of 10% (no windows when the
+// middle part is under 7 trajectories).
+static std::vector<int> mass_windows(int n_adapt) {
+  const int b0 = int(0.15 * n_adapt), b1 = int(0.10 * n_adapt);
+  const int span = n_adapt - b0 - b1;
+  if (span < 7) return {};
+  return {b0, b0 + span / 7, b0 + (3 * span) / 7, b0 + span};
+}
+
+// End of a mass-adaptation window: M^-1 from the window's moments (the sample covariance
+// with its off-diagonal entries shrunk by n / (n + 5) towards its diagonal), factored on the
+// host; the step-size averaging restarts from the current step size. The factor is kept
+// when the estimate is not positive definite (e.g. a coordinate that never moved).
+static int hmc_update_mass(gl_hmc* h, hipStream_t st) {
+  const int d = h->d;
+  const size_t nm = 1 + size_t(d) + size_t(d) * d;
+  std::vector<double> mom(nm);
+  float eps = 0.f;
+  GL_HIP(hipMemcpyAsync(mom.data(), h->a.mom, sizeof(double) * nm, hipMemcpyDeviceToHost, st));
+  GL_HIP(hipMemcpyAsync(&eps, h->a.eps, sizeof(float), hipMemcpyDeviceToHost, st));
+  GL_HIP(hipStreamSynchronize(st));
+  const double n = mom[0];
+  if (!(n >= 2.0)) return GL_OK;
+  std::vector<double> S(size_t(d) * d);
+  const double shrink = n / (n + 5.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      const double mi = mom[1 + i] / n, mj = mom[1 + j] / n;
+      const double cv = (mom[1 + d + size_t(i) * d + j] - n * mi * mj) / (n - 1.0);
+      S[size_t(i) * d + j] = i == j ? cv : shrink * cv;
+    }
+  if (!cholesky(S, d)) return GL_OK;
+  const std::vector<double> SIT = inverse_transpose_lower(S, d);
+  const std::vector<float> chol(S.begin(), S.end()), chol_it(SIT.begin(), SIT.end());
+  const double da0[4] = {std::log(10.0 * double(eps)), 0.0, 0.0, 0.0};
+  GL_HIP(hipMemcpyAsync(h->chol_d, chol.data(), sizeof(float) * d * d, hipMemcpyHostToDevice, st));
+  GL_HIP(hipMemcpyAsync(h->chol_it_d, chol_it.data(), sizeof(float) * d * d,
+                        hipMemcpyHostToDevice, st));
+  GL_HIP(hipMemcpyAsync(h->a.da, da0, sizeof(da0), hipMemcpyHostToDevice, st));
+  GL_HIP(hipStreamSynchronize(st));  // the host vectors go out of scope
+  h->mass_updates++;
+  return GL_OK;
 }
 
 // log p~(z | I) and its gradient at the chains' current positions, then a leapfrog kick
@@ -507,6 +591,13 @@ static int hmc_trajectory(gl_hmc* h, hipStream_t st) {
     rc = hmc_launch1(hmc_mean_kernel, a, kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_finish_kernel, a, a.C * kHmcThreads, kHmcThreads, st);
   if (!rc) rc = hmc_launch1(hmc_adapt_kernel, a, 1, 64, st);
+  for (size_t k = 0; !rc && k + 1 < h->win.size(); ++k) {
+    if (h->done < h->win[k] || h->done >= h->win[k + 1]) continue;
+    if (h->done == h->win[k])
+      rc = hmc_launch1(hmc_window_start_kernel, a, 1 + a.d + a.d * a.d, 256, st);
+    if (!rc) rc = hmc_launch1(hmc_moments_kernel, a, a.d * a.d, 256, st);
+    if (!rc && h->done + 1 == h->win[k + 1]) rc = hmc_update_mass(h, st);
+  }
   if (!rc && a.adapt_len && h->done < h->n_adapt) {  // this trajectory updated T and eps
     const int slot = h->done & 1;
     GL_HIP(hipMemcpyAsync(h->te_host + 2 * slot, a.T, sizeof(float), hipMemcpyDeviceToHost, st));
@@ -535,6 +626,8 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
     return set_error(GL_E_INVALID, "target_accept must be in (0, 1)");
   if (!(o->adapt_frac >= 0.f && o->adapt_frac <= 1.f))
     return set_error(GL_E_INVALID, "adapt_frac must be in [0, 1]");
+  if (o->adapt_mass != 0 && o->adapt_mass != 1)
+    return set_error(GL_E_INVALID, "adapt_mass must be 0 or 1");
   const ModelCfg& c = m->sys.cfg;
   const int C = o->chains, d = c.d;
   gl_fit_opts fo;
@@ -587,14 +680,15 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   h->n_samples = o->n_samples;
   h->n_adapt = int(std::floor(double(o->adapt_frac) * o->n_burn));
   h->target = o->target_accept;
+  if (o->adapt_mass) h->win = mass_windows(h->n_adapt);
   hipStream_t st = (hipStream_t)stream;
   rc = workspace_reserve(m->ws, C, choose_tiles(C, c.H * c.W), c.H * c.W, d, true,
                          beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(h->fb, C, d, pri.data());
   const size_t cd = size_t(C) * d;
   const size_t bytes = sizeof(float) * (4 * cd + 2 * d * d + 2 * C + 12) +
-                       sizeof(double) * (2 * cd + 4 * C + 12 + 2 * d) +
-                       sizeof(float) * size_t(o->n_samples) * cd + 256 * 24;
+                       sizeof(double) * (2 * cd + 4 * C + 12 + 2 * d + 1 + 2 * d + d * d) +
+                       sizeof(float) * size_t(o->n_samples) * cd + 256 * 26;
   if (!rc && hipMalloc(&h->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");
   if (!rc && hipHostMalloc(&h->te_host, 4 * sizeof(float), hipHostMallocDefault) != hipSuccess)
     rc = set_error(GL_E_NOMEM, "hipHostMalloc failed");
@@ -643,6 +737,10 @@ int gl_hmc_create(gl_model* m, const gl_hmc_opts* o, const double* z0, gl_hmc** 
   a.la = reinterpret_cast<double*>(take(sizeof(double) * 4));
   a.zbar = reinterpret_cast<double*>(take(sizeof(double) * 2 * d));
   a.cg = reinterpret_cast<double*>(take(sizeof(double) * C));
+  a.mom = reinterpret_cast<double*>(take(sizeof(double) * (1 + d + d * d)));
+  a.zref = reinterpret_cast<double*>(take(sizeof(double) * d));
+  h->chol_d = chol_d;
+  h->chol_it_d = chol_it_d;
   a.adapt_len = o->adapt_length ? 1 : 0;
   h->max_leapfrog = o->max_leapfrog > 0 ? o->max_leapfrog : 1000;
   a.logl = m->ws.logl;
@@ -728,6 +826,17 @@ int gl_hmc_get_info(gl_hmc* h, gl_hmc_info* out, void* stream) {
   out->trajectories = h->done;
   out->trajectory_length = h->a.adapt_len ? T : float(h->L) * eps;
   out->mean_leapfrog = h->done ? double(h->leapfrogs) / h->done : 0.0;
+  out->mass_updates = h->mass_updates;
+  return GL_OK;
+}
+
+int gl_hmc_get_mass(gl_hmc* h, float* chol, void* stream) {
+  clear_error();
+  if (!h) return set_error(GL_E_INVALID, "state is NULL");
+  int rc = check_device_ptr(chol, "chol");
+  if (rc) return rc;
+  GL_HIP(hipMemcpyAsync(chol, h->chol_d, sizeof(float) * h->d * h->d, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
   return GL_OK;
 }
 

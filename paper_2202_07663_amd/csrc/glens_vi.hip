@@ -21,7 +21,8 @@
 //            lane reads the iteration's old state; lane 0 also records the loss
 //            E[f] - sum_i log L_ii - (d/2)(1 + log 2 pi).
 // The learning rate rises from 0 to lr_max as lr_max (1 - (1 - k / warmup)^2) over the
-// first `warmup` iterations (the paper: 0 -> 1e-3 over 500), then stays at lr_max.
+// first `warmup` iterations (the paper: 0 -> 1e-3 over 500), then stays at lr_max, or, when
+// a final rate is given, falls geometrically to it on the last iteration.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -255,7 +256,7 @@ using namespace glens;
 struct gl_vi {
   gl_model* model = nullptr;
   int n = 0, d = 0, nc = 0, K = 0, k = 0, cur = 0, warmup = 0;
-  float lr_max = 0.f;
+  float lr_max = 0.f, lr_final = 0.f;
   char* base = nullptr;
   double* x[2] = {nullptr, nullptr};
   ViArgs a{};
@@ -268,9 +269,14 @@ static int vi_check_launch() {
 }
 
 static float vi_learning_rate(const gl_vi* v, int k) {
-  if (v->warmup <= 0) return v->lr_max;
-  const double frac = 1.0 - double(std::min(k, v->warmup)) / v->warmup;
-  return float(v->lr_max * (1.0 - frac * frac));
+  if (k < v->warmup) {
+    const double frac = 1.0 - double(k) / v->warmup;
+    return float(v->lr_max * (1.0 - frac * frac));
+  }
+  const int span = v->K - 1 - v->warmup;
+  if (v->lr_final <= 0.f || span <= 0) return v->lr_max;
+  const double t = std::min(1.0, double(k - v->warmup) / span);
+  return float(double(v->lr_max) * std::pow(double(v->lr_final) / v->lr_max, t));
 }
 
 static int vi_iteration(gl_vi* v, hipStream_t st) {
@@ -328,6 +334,9 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
     return set_error(GL_E_INVALID, "need n_samples >= 1, K >= 1, lr_warmup >= 0");
   if (!(o->lr_max >= 0.f) || !std::isfinite(o->lr_max))
     return set_error(GL_E_INVALID, "lr_max must be finite and >= 0");
+  if (!(o->lr_final >= 0.f) || !std::isfinite(o->lr_final) ||
+      (o->lr_final > 0.f && !(o->lr_max > 0.f)))
+    return set_error(GL_E_INVALID, "lr_final must be finite and >= 0 (> 0 needs lr_max > 0)");
   if (!(o->init_sd > 0.f) || !std::isfinite(o->init_sd))
     return set_error(GL_E_INVALID, "init_sd must be > 0");
   const ModelCfg& c = m->sys.cfg;
@@ -350,6 +359,7 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
   v->K = o->K;
   v->warmup = o->lr_warmup;
   v->lr_max = o->lr_max;
+  v->lr_final = o->lr_final;
   hipStream_t st = (hipStream_t)stream;
   rc = workspace_reserve(m->ws, n, choose_tiles(n, c.H * c.W), c.H * c.W, d, true,
                          beta_per_particle(c));

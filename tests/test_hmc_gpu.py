@@ -248,3 +248,49 @@ def test_length_adaptation_survives_a_far_rejected_chain(G, sie40):
     assert np.isfinite(info["trajectory_length"]) and info["trajectory_length"] > 0
     assert np.isfinite(info["step_size"]) and info["step_size"] > 0
     assert np.all(np.isfinite(h.samples().cpu().numpy()[:, np.arange(C) != 3]))
+
+
+def test_mass_adaptation(G, sie40):
+    """Windowed re-estimation of M^-1 (adapt_mass). From a mass matrix with the wrong widths
+    (the posterior's diagonal scaled by factors of 1/8 .. 8) and no correlations, the three
+    window estimates replace it; the last one matches the posterior covariance (the Laplace
+    approximation from the oracle) in whitened units to within sampling error, and the
+    samples match the Laplace posterior. Without windows (a burn-in too short for them) the
+    factor stays the one given."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    d = z_c.size
+    C, nb, ns = 64, 400, 300
+    rng = np.random.default_rng(21)
+    z0 = z_c + rng.normal(size=(C, d)) @ np.linalg.cholesky(cov).T
+    bad = np.diag(cov) * np.exp(rng.uniform(-np.log(64), np.log(64), d))
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 5, nb, ns, priors, step_size=0.3, seed=23, inv_mass=bad,
+              z0=torch.from_numpy(z0).cuda(), adapt_mass=True)
+    h.run()
+    info = h.info()
+    F = h.mass_chol().cpu().numpy().astype(np.float64)
+    Lc = np.linalg.cholesky(cov)
+    W = np.linalg.solve(Lc, np.linalg.solve(Lc, F @ F.T).T)  # Lc^-1 (F F^T) Lc^-T
+    ev = np.linalg.eigvalsh((W + W.T) / 2)
+    th = h.samples().cpu().numpy().astype(np.float64)
+    z = ofit.bijector_inverse(th.reshape(-1, d), priors).reshape(th.shape)
+    sd = np.sqrt(np.diag(cov))
+    mean_err = np.abs(z.mean(axis=(0, 1)) - z_c) / sd
+    sd_ratio = z.std(axis=(0, 1)) / sd
+    rhat, ess = dg.split_rhat(z), dg.ess(z)
+    _say("mass updates", info["mass_updates"], "whitened eigenvalues", ev.min(), ev.max(),
+         "eps", info["step_size"], "accept", info["accept_mean"], "rhat", rhat.max(), "ess",
+         ess.min(), "mean err", mean_err.max(), "sd ratio", sd_ratio.min(), sd_ratio.max())
+    assert info["mass_updates"] == 3
+    assert np.allclose(F, np.tril(F))
+    assert ev.min() > 0.6 and ev.max() < 1.5
+    assert rhat.max() < 1.05 and ess.min() > 500
+    assert mean_err.max() < 0.15 and np.all(np.abs(sd_ratio - 1) < 0.12)
+    # n_adapt = floor(0.8 x 5) = 4 trajectories: too few for windows
+    h2 = G.HMC(model, 8, 3, 5, 2, priors, step_size=0.3, seed=1, inv_mass=bad,
+               z0=torch.from_numpy(z0[:8]).cuda(), adapt_mass=True)
+    h2.run()
+    assert h2.info()["mass_updates"] == 0
+    np.testing.assert_allclose(h2.mass_chol().cpu().numpy(), np.diag(np.sqrt(bad)), rtol=1e-6)
+    with pytest.raises(G.GlError):
+        G.HMC(model, 4, 3, 1, 1, priors, adapt_mass=2)

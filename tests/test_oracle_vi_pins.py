@@ -69,6 +69,23 @@ def test_learning_rate_schedule():
     assert all(b > a for a, b in zip(lr, lr[1:]))
 
 
+def test_learning_rate_geometric_decay():
+    """The optional decay after the warm-up: lr_max at the end of the warm-up, lr_final on
+    the last iteration, their geometric mean half-way (a constant ratio per iteration), and
+    the paper's constant rate when lr_final is 0."""
+    K, w = 1001, 200
+    assert math.isclose(vi.learning_rate(w, 3e-3, w, 1e-5, K), 3e-3)
+    assert math.isclose(vi.learning_rate(K - 1, 3e-3, w, 1e-5, K), 1e-5)
+    assert math.isclose(vi.learning_rate(w + 400, 3e-3, w, 1e-5, K), math.sqrt(3e-3 * 1e-5))
+    r = [vi.learning_rate(k + 1, 3e-3, w, 1e-5, K) / vi.learning_rate(k, 3e-3, w, 1e-5, K)
+         for k in range(w, K - 1)]
+    assert max(r) - min(r) < 1e-12 and math.isclose(r[0], (1e-5 / 3e-3) ** (1 / 800))
+    assert math.isclose(vi.learning_rate(199, 3e-3, w, 1e-5, K),
+                        vi.learning_rate(199, 3e-3, w))
+    assert vi.learning_rate(900, 3e-3, w, 0.0, K) == 3e-3
+    assert vi.learning_rate(0, 3e-3, 0, 1e-5, K) == 3e-3
+
+
 def _quadratic(A, c):
     def fg(z):
         u = z - c

@@ -54,13 +54,15 @@ def systems():
 
 
 @pytest.mark.parametrize("name", ["sie40", "vi40"])
-@pytest.mark.parametrize("k", [0, 37, 700])
-def test_vi_iteration_parity(G, systems, name, k):
+@pytest.mark.parametrize("k,lr_final", [(0, 0.0), (37, 0.0), (700, 0.0), (700, 1e-5),
+                                        (999, 1e-5)])
+def test_vi_iteration_parity(G, systems, name, k, lr_final):
     """One iteration on the GPU (draws, z = mu + L eps in FP64 rounded to FP32 for the
     likelihood, pipeline, prior terms, pathwise estimate, Adam) against the oracle's FP64
     iteration with the same Philox draws. Adam moments are warm (s >= the squared gradient
     scale) so the step is a smooth function of the gradient estimate: the updates agree to
-    0.5% of the learning rate, and the recorded loss to the log-likelihood bar."""
+    0.5% of the learning rate, and the recorded loss to the log-likelihood bar. lr_final > 0:
+    iterations of the geometric decay after the warm-up (the last at k = K - 1)."""
     spec, obs, priors, fg, z_c, cov = systems[name]
     d = spec.d
     n, seed = 48, 77
@@ -77,9 +79,9 @@ def test_vi_iteration_parity(G, systems, name, k):
     s0 = scale ** 2 * rng.uniform(1, 2, g.shape)
     x0 = np.concatenate([mu, v])
     K = 1000
-    lr = ovi.learning_rate(k, 1e-3, 500)
+    lr = ovi.learning_rate(k, 1e-3, 500, lr_final, K)
     vi = G.VI(G.Model.from_spec(spec, obs), n, K, priors, mu, lr_max=1e-3, lr_warmup=500,
-              seed=seed)
+              seed=seed, lr_final=lr_final)
     vi.set_state(x0, m0, s0, k)
     vi.step(1)
     st = vi.get_state()
@@ -207,7 +209,8 @@ def test_vi_options_and_non_finite_iterations(G, systems):
     and records a NaN loss."""
     spec, obs, priors, fg, z_c, cov = systems["vi40"]
     model = G.Model.from_spec(spec, obs)
-    for kw in ({"init_sd": 0.0}, {"lr_max": -1.0}, {"lr_warmup": -1}):
+    for kw in ({"init_sd": 0.0}, {"lr_max": -1.0}, {"lr_warmup": -1}, {"lr_final": -1e-5},
+               {"lr_final": float("inf")}, {"lr_max": 0.0, "lr_final": 1e-5}):
         with pytest.raises(G.GlError):
             G.VI(model, 8, 10, priors, z_c, **kw)
     with pytest.raises(G.GlError):
