@@ -6,7 +6,9 @@ posterior covariance (here inv_mass = M^-1, diagonal or dense);
 Hamiltonian H = -log p~(z | I) + p^T M^-1 p / 2; leapfrog integration with step eps and
 L steps; Metropolis acceptance min(1, exp(H0 - H1)). The step size is tuned by the dual
 averaging of Hoffman & Gelman (2014, Sec. 3.2) towards a target acceptance probability
-(0.75 in the paper) during the first part of burn-in.
+(0.75 in the paper) during the first part of burn-in. The optional windowed re-estimation of
+M^-1 (not in the paper) is given by its window schedule and estimator (mass_windows,
+window_inv_mass).
 """
 from __future__ import annotations
 
@@ -204,3 +206,28 @@ def chees_run(fg, z, inv_mass, eps, T0, n_iter, rng, target=None):
         keep = rng.uniform(size=len(z)) < acc
         z = np.where(keep[:, None], z1, z)
     return ad, z
+
+
+def mass_windows(n_adapt):
+    """Window boundaries of the optional mass adaptation (not in the paper; Stan's windowed
+    scheme): an initial buffer of floor(0.15 n_adapt) trajectories, three windows of lengths in
+    the ratio 1 : 2 : 4 (cut at floor(span / 7) and floor(3 span / 7)), a terminal buffer of
+    floor(0.10 n_adapt); window k holds the positions after trajectories [b[k], b[k + 1]).
+    No windows when they would span fewer than 7 trajectories."""
+    b0, b1 = int(0.15 * n_adapt), int(0.10 * n_adapt)
+    span = n_adapt - b0 - b1
+    if span < 7:
+        return []
+    return [b0, b0 + span // 7, b0 + (3 * span) // 7, b0 + span]
+
+
+def window_inv_mass(Z):
+    """M^-1 estimated from a window's positions Z [n, d]: the sample covariance (divisor
+    n - 1) with its off-diagonal entries scaled by n / (n + 5), i.e. shrunk towards its
+    diagonal."""
+    Z = np.asarray(Z, np.float64)
+    n = Z.shape[0]
+    dev = Z - Z.mean(axis=0)
+    S = dev.T @ dev / (n - 1)
+    w = n / (n + 5.0)
+    return w * S + (1.0 - w) * np.diag(np.diag(S))

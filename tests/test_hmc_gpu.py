@@ -294,3 +294,31 @@ def test_mass_adaptation(G, sie40):
     np.testing.assert_allclose(h2.mass_chol().cpu().numpy(), np.diag(np.sqrt(bad)), rtol=1e-6)
     with pytest.raises(G.GlError):
         G.HMC(model, 4, 3, 1, 1, priors, adapt_mass=2)
+
+
+def test_mass_estimate_matches_the_oracle(G, sie40):
+    """The window estimate itself against the oracle's estimator, on positions known
+    exactly: with a step size of 30 posterior widths every proposal is rejected, and a
+    target acceptance of 1e-6 keeps the adapted step there, so each chain stays at its start
+    and a window of w trajectories holds each start w times. After the last window M^-1 is the
+    oracle's window_inv_mass of those positions (window lengths from its mass_windows), to
+    the FP32 rounding of the factor."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    d = z_c.size
+    C, nb = 32, 20
+    rng = np.random.default_rng(8)
+    z0 = z_c + rng.normal(size=(C, d)) @ np.linalg.cholesky(cov).T
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 3, nb, 1, priors, step_size=30.0, target_accept=1e-6, adapt_frac=1.0,
+              seed=29, inv_mass=cov, z0=torch.from_numpy(z0).cuda(), adapt_mass=True)
+    h.run()
+    info = h.info()
+    b = ohmc.mass_windows(nb)
+    ref = np.linalg.cholesky(ohmc.window_inv_mass(np.tile(z0, (b[3] - b[2], 1))))
+    F = h.mass_chol().cpu().numpy().astype(np.float64)
+    th = h.samples().cpu().numpy()[0]
+    _say("windows", b, "accept", info["accept_mean"], "eps", info["step_size"],
+         "max |F - ref| / max |ref|", np.abs(F - ref).max() / np.abs(ref).max())
+    assert info["mass_updates"] == 3 and info["accept_mean"] == 0.0
+    np.testing.assert_allclose(th, ofit.bijector(z0, priors), rtol=2e-6, atol=1e-7)
+    np.testing.assert_allclose(F, ref, rtol=2e-5, atol=2e-6 * np.abs(ref).max())

@@ -216,3 +216,39 @@ def test_chees_adaptation_finds_the_optimal_length(scale, inv_mass, want):
                           eps, 0.5 * want, 600, rng)
     assert abs(ad.final() / want - 1.0) < 0.08, (ad.final(), want)
     assert abs(np.std(z) / scale - 1.0) < 0.05  # still samples the target
+
+
+def test_mass_windows_schedule():
+    """Initial buffer 15%, windows 1 : 2 : 4, terminal buffer 10%, none below 7 trajectories
+    of windows (values worked by hand)."""
+    assert hmc.mass_windows(200) == [30, 51, 94, 180]  # 30 + 150: 21, 43, 86
+    assert hmc.mass_windows(800) == [120, 205, 377, 720]  # 120 + 600: 85, 172, 343
+    assert hmc.mass_windows(20) == [3, 5, 9, 18]
+    assert hmc.mass_windows(9) == [1, 2, 4, 9]  # span 8 (the buffers floor to 1 and 0)
+    assert hmc.mass_windows(7) == []  # span 7 - 1 - 0 = 6
+    assert hmc.mass_windows(8) == [1, 2, 4, 8]  # span 7
+    assert hmc.mass_windows(0) == [] and hmc.mass_windows(4) == []
+    for n in range(8, 2000, 37):
+        b = hmc.mass_windows(n)
+        lengths = np.diff(b)
+        assert b[0] == int(0.15 * n) and b[-1] == n - int(0.10 * n)
+        assert np.all(lengths >= 0) and lengths[2] >= lengths[1] >= lengths[0]
+
+
+def test_window_inv_mass():
+    """The sample covariance (numpy's, divisor n - 1) on the diagonal, its off-diagonal
+    scaled by n / (n + 5); positive definite even from fewer samples than dimensions; close
+    to the generating covariance for a large Gaussian sample."""
+    rng = np.random.default_rng(3)
+    d = 6
+    A = rng.normal(size=(d, d))
+    cov = A @ A.T + 0.1 * np.eye(d)
+    Z = rng.multivariate_normal(np.arange(d), cov, size=40)
+    S = np.cov(Z.T)
+    M = hmc.window_inv_mass(Z)
+    np.testing.assert_allclose(np.diag(M), np.diag(S), rtol=1e-12)
+    off = ~np.eye(d, dtype=bool)
+    np.testing.assert_allclose(M[off], S[off] * 40 / 45, rtol=1e-12)
+    assert np.all(np.linalg.eigvalsh(hmc.window_inv_mass(Z[:4])) > 0)
+    big = rng.multivariate_normal(np.zeros(d), cov, size=200000)
+    np.testing.assert_allclose(hmc.window_inv_mass(big), cov, atol=0.02 * np.abs(cov).max())
