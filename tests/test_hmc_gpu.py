@@ -322,3 +322,34 @@ def test_mass_estimate_matches_the_oracle(G, sie40):
     assert info["mass_updates"] == 3 and info["accept_mean"] == 0.0
     np.testing.assert_allclose(th, ofit.bijector(z0, priors), rtol=2e-6, atol=1e-7)
     np.testing.assert_allclose(F, ref, rtol=2e-5, atol=2e-6 * np.abs(ref).max())
+
+
+def test_mass_and_length_adaptation_together(G, sie40):
+    """Mass adaptation with the trajectory length adapted too (ChEES): from the same mass
+    matrix with the wrong widths, the length settles on a finite value, the three window
+    estimates are taken, and the samples match the Laplace posterior."""
+    spec, obs, priors, fg, z_c, cov = sie40
+    d = z_c.size
+    C, nb, ns = 64, 300, 200
+    rng = np.random.default_rng(31)
+    z0 = z_c + rng.normal(size=(C, d)) @ np.linalg.cholesky(cov).T
+    bad = np.diag(cov) * np.exp(rng.uniform(-np.log(64), np.log(64), d))
+    model = G.Model.from_spec(spec, obs)
+    h = G.HMC(model, C, 5, nb, ns, priors, step_size=0.3, seed=37, inv_mass=bad,
+              z0=torch.from_numpy(z0).cuda(), adapt_mass=True, adapt_length=True,
+              max_leapfrog=50)
+    h.run()
+    info = h.info()
+    th = h.samples().cpu().numpy().astype(np.float64)
+    z = ofit.bijector_inverse(th.reshape(-1, d), priors).reshape(th.shape)
+    sd = np.sqrt(np.diag(cov))
+    mean_err = np.abs(z.mean(axis=(0, 1)) - z_c) / sd
+    sd_ratio = z.std(axis=(0, 1)) / sd
+    rhat = dg.split_rhat(z)
+    _say("T", info["trajectory_length"], "eps", info["step_size"], "mean L",
+         info["mean_leapfrog"], "updates", info["mass_updates"], "rhat", rhat.max(),
+         "mean err", mean_err.max(), "sd ratio", sd_ratio.min(), sd_ratio.max())
+    assert info["mass_updates"] == 3
+    assert np.isfinite(info["trajectory_length"]) and info["trajectory_length"] > 0
+    assert rhat.max() < 1.05
+    assert mean_err.max() < 0.15 and np.all(np.abs(sd_ratio - 1) < 0.12)
