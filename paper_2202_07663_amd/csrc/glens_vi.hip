@@ -83,11 +83,16 @@ __device__ __forceinline__ double chol_entry(const double* v, int i, int j) {
   return i == j ? exp(e) : e;
 }
 
-// z = mu + L eps for one sample (block), eps drawn with tag `tag` at iteration `k`.
+// z = mu + L eps for one sample (block), eps drawn with tag `tag` at iteration `k`. The
+// factor is first copied to LDS (its diagonal exponentiated there): each lane's row then
+// reads it without an L2 round trip per entry.
 __device__ __forceinline__ void draw_sample(const double* mu, const double* v, int d, int s,
                                             int k, uint32_t tag, uint32_t seed_lo,
                                             uint32_t seed_hi, double* s_eps, double* eps_out,
                                             float* z32_out, double* z64_out) {
+  __shared__ double s_l[kMaxParams * (kMaxParams + 1) / 2];
+  const int nc = d * (d + 1) / 2;
+  for (int q = threadIdx.x; q < nc; q += kViThreads) s_l[q] = v[q];
   for (int j = threadIdx.x; j < d; j += kViThreads) {
     uint32_t w[4] = {uint32_t(s), uint32_t(j), uint32_t(k), tag};
     philox4x32_10(w, seed_lo, seed_hi);
@@ -96,10 +101,16 @@ __device__ __forceinline__ void draw_sample(const double* mu, const double* v, i
     s_eps[j] = e;
     if (eps_out) eps_out[size_t(s) * d + j] = e;
   }
+  __syncthreads();  // the raw factor is in LDS
+  for (int i = threadIdx.x; i < d; i += kViThreads) {
+    const int q = i * (i + 1) / 2 + i;
+    s_l[q] = exp(s_l[q]);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < d; i += kViThreads) {
     double zi = mu[i];
-    for (int j = 0; j <= i; ++j) zi += chol_entry(v, i, j) * s_eps[j];
+    const double* li = s_l + i * (i + 1) / 2;
+    for (int j = 0; j <= i; ++j) zi += li[j] * s_eps[j];
     if (z32_out) z32_out[size_t(s) * d + i] = float(zi);
     if (z64_out) z64_out[size_t(s) * d + i] = zi;
   }
@@ -175,6 +186,7 @@ __global__ void __launch_bounds__(256) vi_reduce_kernel(ViArgs a) {
   if (threadIdx.x == 0) {
     double fsum = 0.0;
     int nok = 0;
+#pragma unroll 8
     for (int t = 0; t < ns; ++t) {
       const double fs = a.f[s0 + t];
       if (!isfinite(fs)) continue;
@@ -196,7 +208,8 @@ __global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a, int chunks) {
   int i, j;
   vi_entry(q, d, i, j);
   double sum = 0.0, fsum = 0.0, nokd = 0.0;
-  for (int c = 0; c < chunks; ++c) {
+#pragma unroll 8
+  for (int c = 0; c < chunks; ++c) {  // in chunk order (unrolled: the loads go out together)
     const double* pc = a.part + size_t(c) * (nx + 2);
     sum += pc[q];
     fsum += pc[nx];
