@@ -95,6 +95,7 @@ __device__ __forceinline__ void stage_factor(const float* m, int d, float* s_m) 
 __device__ __forceinline__ void chol_t_times(const float* chol, int d, const float* x, float* v) {
   for (int j = threadIdx.x; j < d; j += kHmcThreads) {
     float s = 0.f;
+#pragma unroll 4
     for (int i = j; i < d; ++i) s += chol[i * d + j] * x[i];
     v[j] = s;
   }
@@ -122,6 +123,7 @@ __device__ __forceinline__ void kick_drift(const HmcArgs& a, const float* s_g, f
   __syncthreads();
   for (int j = threadIdx.x; j < a.d; j += kHmcThreads) {
     float s = 0.f;
+#pragma unroll 4
     for (int i = 0; i <= j; ++i) s += s_chol[j * a.d + i] * s_v[i];
     const double zn = a.z[row + j] + double(eps) * s;
     a.z[row + j] = zn;

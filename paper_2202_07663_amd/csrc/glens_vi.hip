@@ -46,6 +46,7 @@ struct ViArgs {
   int n, d, nc, k;
   float lr;
   float beta1, beta2, adam_eps;
+  double bc1, bc2;     // Adam's bias corrections 1 - beta^(k + 1) of this iteration
   const Prior* prior;
   const double* x;     // [d + nc] current (mu, v)
   double* x_new;       // [d + nc] next (mu, v)
@@ -228,13 +229,12 @@ __global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a, int chunks) {
     for (int t = 0; t < d; ++t) logdet += v[t * (t + 1) / 2 + t];
     a.loss[a.k] = fsum / nok - logdet - 0.5 * d * (1.0 + 1.8378770664093453);
   }
-  const int t = a.k + 1;
   const double mq = a.beta1 * a.m[q] + (1.0 - a.beta1) * gq;
   const double sq = a.beta2 * a.s[q] + (1.0 - a.beta2) * gq * gq;
   a.m[q] = mq;
   a.s[q] = sq;
-  const double mhat = mq / (1.0 - pow(double(a.beta1), t));
-  const double shat = sq / (1.0 - pow(double(a.beta2), t));
+  const double mhat = mq / a.bc1;
+  const double shat = sq / a.bc2;
   a.x_new[q] = a.x[q] - a.lr * mhat / (sqrt(shat) + a.adam_eps);
 }
 
@@ -301,6 +301,8 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
   ViArgs& a = v->a;
   a.k = v->k;
   a.lr = vi_learning_rate(v, v->k);
+  a.bc1 = 1.0 - std::pow(double(a.beta1), double(v->k + 1));
+  a.bc2 = 1.0 - std::pow(double(a.beta2), double(v->k + 1));
   a.x = v->x[v->cur];
   a.x_new = v->x[1 - v->cur];
   a.logl = m->ws.logl;
