@@ -177,9 +177,10 @@ def workload():
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
                    chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100,
                    adapt_length=True, vi_lr=1e-3, vi_warmup=500, vi_init_sd=1e-3,
-                   map_result=None, vi_lr_final=0.0, adapt_mass=False):
+                   map_result=None, vi_lr_final=0.0, adapt_mass=False, full=False):
     """map_result: (fit result, seconds) of a MAP stage already run with these settings (the
-    stage is then not run again; its time is reported as measured there)."""
+    stage is then not run again; its time is reported as measured there). full: also return
+    the posterior means and standard deviations, split R-hat and ESS of every parameter."""
     import torch
     import synth
     import paper_2202_07663_amd as G
@@ -242,8 +243,70 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
         "truth_pull_median": round(float(np.median(pull)), 3),
         "truth_pull_max": round(float(np.max(pull)), 3),
         "posterior_mean_sd_truth": light,
+        **({"post_mean": mean.tolist(), "post_sd": sd.tolist(), "rhat": np.asarray(rhat).tolist(),
+            "ess": np.asarray(ess).tolist()} if full else {}),
         "paper_context": "Table 1: 17 s + 52 s + 36 s = 105 s on 4x A100 (about 6 min on one) "
                          "for the paper's reference system (another PSF and truth)",
+    }
+
+
+def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300):
+    """The pipeline at Table 1's sizes on n_systems systems drawn from the paper's simulation
+    distribution (eq. sim-dist; the 80x80 configuration of its Sec. 3), each observed as a
+    GPU-simulated image plus seeded noise: per parameter the mean and spread of the scaled
+    errors z = (posterior mean - truth) / posterior sd, the share of truths within one and
+    two posterior sd, the largest split R-hat and the smallest ESS over the systems (the
+    statistics of the paper's Table 2). n_map, k_map: the MAP stage's starts and steps."""
+    import torch
+    import synth
+    import paper_2202_07663_amd as G
+    sp = synth.spec_paper80()
+    zs, rh, es, secs, chi, acc = [], [], [], [], [], []
+    names = None
+    for i in range(n_systems):
+        seed = seed0 + i
+        truth = synth.draw_truth(sp, seed)
+        sim = G.Model.from_spec(sp)
+        names = sim.names
+        clean = sim.simulate(torch.from_numpy(truth[None, :]).cuda())[0].cpu().numpy()
+        sim.close()
+        obs = synth.add_noise(clean, seed, sp.sigma_bkg, sp.t_exp)
+        r = pipeline_bench(sp, obs, truth, seed=seed, n_map=n_map, k_map=k_map, n_vi=500,
+                           k_vi=1000, chains=50, L=5, adapt_mass=adapt_mass, full=True)
+        sd = np.maximum(np.asarray(r["post_sd"]), 1e-30)
+        zs.append((np.asarray(r["post_mean"]) - truth) / sd)
+        rh.append(r["rhat"])
+        es.append(r["ess"])
+        secs.append(r["seconds"]["total"])
+        chi.append(r["map_chi2nu"])
+        acc.append(r["hmc_accept"])
+        print(f"recovery {i + 1}/{n_systems}: chi2nu {r['map_chi2nu']:.3f} "
+              f"rhat {max(r['rhat']):.3f} |z| max {np.abs(zs[-1]).max():.2f}", file=sys.stderr,
+              flush=True)
+    z, rh, es = np.asarray(zs), np.asarray(rh), np.asarray(es)
+    per = {n: {"mu_z": round(float(z[:, j].mean()), 3), "sd_z": round(float(z[:, j].std()), 3),
+               "within_1sd": round(float(np.mean(np.abs(z[:, j]) < 1)), 3),
+               "max_rhat": round(float(rh[:, j].max()), 4),
+               "min_ess": round(float(es[:, j].min()), 1)} for j, n in enumerate(names)}
+    return {
+        "workload": "paper80 (eq. sim-dist draws, seeds %d-%d)" % (seed0, seed0 + n_systems - 1),
+        "systems": n_systems,
+        "config": {"map": [n_map, k_map], "vi": [500, 1000], "hmc": {"chains": 50, "L0": 5,
+                   "burn": 250, "samples": 750, "adapt_length": True,
+                   "adapt_mass": bool(adapt_mass)}},
+        "seconds_per_system": {"mean": round(float(np.mean(secs)), 3),
+                               "max": round(float(np.max(secs)), 3)},
+        "map_chi2nu": {"median": round(float(np.median(chi)), 4),
+                       "max": round(float(np.max(chi)), 4)},
+        "hmc_accept_mean": round(float(np.mean(acc)), 4),
+        "within_1sd": round(float(np.mean(np.abs(z) < 1)), 4),
+        "within_2sd": round(float(np.mean(np.abs(z) < 2)), 4),
+        "abs_mu_z_max": round(float(np.abs(z.mean(axis=0)).max()), 3),
+        "max_rhat": round(float(rh.max()), 4),
+        "systems_rhat_below_1_05": int(np.sum(rh.max(axis=1) < 1.05)),
+        "min_ess": round(float(es.min()), 1),
+        "per_parameter": per,
+        "paper_context": "Sec. 3, Table 2: 100 systems, largest R-hat 1.017, smallest ESS 26 822",
     }
 
 
@@ -621,6 +684,11 @@ def main():
                          "(--serve-systems requests; e.g. 500) and print its JSON line")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the MAP -> VI -> HMC pipeline measurement")
+    ap.add_argument("--recovery", type=int, default=0, metavar="N",
+                    help="only the pipeline on N systems of the paper's simulation "
+                         "distribution (posterior calibration and convergence)")
+    ap.add_argument("--recovery-map", type=int, nargs=2, default=[300, 300],
+                    metavar=("STARTS", "STEPS"), help="MAP budget of --recovery (Table 1's)")
     ap.add_argument("--c4-only", action="store_true",
                     help="run only the whole fit of the 60x60 EPL + shapelet system (MAP, VI, "
                          "HMC) and print its JSON")
@@ -656,6 +724,11 @@ def main():
     import torch
     import paper_2202_07663_amd as G
 
+    if args.recovery > 0:
+        r = recovery_bench(args.recovery, n_map=args.recovery_map[0],
+                           k_map=args.recovery_map[1])
+        print(json.dumps(_finite({"recovery": r}), allow_nan=False), flush=True)
+        return
     if args.c4_only:
         import synth
         print(json.dumps(_finite(c4_bench(G, synth.spec_c2())), allow_nan=False), flush=True)
