@@ -177,7 +177,8 @@ def workload():
 def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k_vi=1000,
                    chains=64, L=10, n_burn=250, n_samples=750, max_leapfrog=100,
                    adapt_length=True, vi_lr=1e-3, vi_warmup=500, vi_init_sd=1e-3,
-                   map_result=None, vi_lr_final=0.0, adapt_mass=False, full=False):
+                   map_result=None, vi_lr_final=0.0, adapt_mass=False, full=False,
+                   priors=None):
     """map_result: (fit result, seconds) of a MAP stage already run with these settings (the
     stage is then not run again; its time is reported as measured there). full: also return
     the posterior means and standard deviations, split R-hat and ESS of every parameter."""
@@ -185,7 +186,8 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     import synth
     import paper_2202_07663_amd as G
     from paper_2202_07663_amd import diagnostics as dg
-    priors = synth.fit_priors(spec)
+    if priors is None:
+        priors = synth.fit_priors(spec)
     model = G.Model.from_spec(spec, obs)
     torch.cuda.synchronize()
     if map_result is None:
@@ -244,24 +246,33 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
         "truth_pull_max": round(float(np.max(pull)), 3),
         "posterior_mean_sd_truth": light,
         **({"post_mean": mean.tolist(), "post_sd": sd.tolist(), "rhat": np.asarray(rhat).tolist(),
-            "ess": np.asarray(ess).tolist()} if full else {}),
+            "ess": np.asarray(ess).tolist(), "post_median": np.median(flat, axis=0).tolist(),
+            "map_theta": np.asarray(r["theta_best"], np.float64).tolist(),
+            "truth_rank": np.mean(flat < truth[None, :], axis=0).tolist()} if full else {}),
         "paper_context": "Table 1: 17 s + 52 s + 36 s = 105 s on 4x A100 (about 6 min on one) "
                          "for the paper's reference system (another PSF and truth)",
     }
 
 
-def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300):
+def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300,
+                   prior="paper", noise="poisson"):
     """The pipeline at Table 1's sizes on n_systems systems drawn from the paper's simulation
     distribution (eq. sim-dist; the 80x80 configuration of its Sec. 3), each observed as a
     GPU-simulated image plus seeded noise: per parameter the mean and spread of the scaled
     errors z = (posterior mean - truth) / posterior sd, the share of truths within one and
     two posterior sd, the largest split R-hat and the smallest ESS over the systems (the
-    statistics of the paper's Table 2). n_map, k_map: the MAP stage's starts and steps."""
+    statistics of the paper's Table 2). n_map, k_map: the MAP stage's starts and steps.
+    prior: "paper" (the broadened prior of eq. sim-dist, as the paper fits) or "sim" (the
+    simulation distribution itself, under which the posterior is calibrated by construction).
+    noise: "poisson" (shot noise plus Gaussian background, Sec. 2.1.2) or "gauss" (Gaussian
+    of the likelihood's own variance). Besides the posterior mean, the scaled errors of the
+    posterior median and of the MAP point and the truth's rank among the samples are kept,
+    which separate a shift of the whole posterior from its skewness."""
     import torch
     import synth
     import paper_2202_07663_amd as G
     sp = synth.spec_paper80()
-    zs, rh, es, secs, chi, acc = [], [], [], [], [], []
+    zs, rh, es, secs, chi, acc, zmed, zmap, ranks = [], [], [], [], [], [], [], [], []
     names = None
     for i in range(n_systems):
         seed = seed0 + i
@@ -270,11 +281,18 @@ def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300)
         names = sim.names
         clean = sim.simulate(torch.from_numpy(truth[None, :]).cuda())[0].cpu().numpy()
         sim.close()
-        obs = synth.add_noise(clean, seed, sp.sigma_bkg, sp.t_exp)
+        if noise == "poisson":
+            obs = synth.add_noise(clean, seed, sp.sigma_bkg, sp.t_exp)
+        else:
+            obs = synth.add_gaussian_noise(clean, seed, sp.sigma_bkg, sp.t_exp)
         r = pipeline_bench(sp, obs, truth, seed=seed, n_map=n_map, k_map=k_map, n_vi=500,
-                           k_vi=1000, chains=50, L=5, adapt_mass=adapt_mass, full=True)
+                           k_vi=1000, chains=50, L=5, adapt_mass=adapt_mass, full=True,
+                           priors=synth.fit_priors(sp, matched=(prior == "sim")))
         sd = np.maximum(np.asarray(r["post_sd"]), 1e-30)
         zs.append((np.asarray(r["post_mean"]) - truth) / sd)
+        zmed.append((np.asarray(r["post_median"]) - truth) / sd)
+        zmap.append((np.asarray(r["map_theta"]) - truth) / sd)
+        ranks.append(r["truth_rank"])
         rh.append(r["rhat"])
         es.append(r["ess"])
         secs.append(r["seconds"]["total"])
@@ -284,13 +302,18 @@ def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300)
               f"rhat {max(r['rhat']):.3f} |z| max {np.abs(zs[-1]).max():.2f}", file=sys.stderr,
               flush=True)
     z, rh, es = np.asarray(zs), np.asarray(rh), np.asarray(es)
+    zmed, zmap, ranks = np.asarray(zmed), np.asarray(zmap), np.asarray(ranks)
     per = {n: {"mu_z": round(float(z[:, j].mean()), 3), "sd_z": round(float(z[:, j].std()), 3),
+               "mu_z_median": round(float(zmed[:, j].mean()), 3),
+               "mu_z_map": round(float(zmap[:, j].mean()), 3),
+               "mean_rank": round(float(ranks[:, j].mean()), 3),
                "within_1sd": round(float(np.mean(np.abs(z[:, j]) < 1)), 3),
                "max_rhat": round(float(rh[:, j].max()), 4),
                "min_ess": round(float(es[:, j].min()), 1)} for j, n in enumerate(names)}
     return {
         "workload": "paper80 (eq. sim-dist draws, seeds %d-%d)" % (seed0, seed0 + n_systems - 1),
         "systems": n_systems,
+        "prior": prior, "noise": noise,
         "config": {"map": [n_map, k_map], "vi": [500, 1000], "hmc": {"chains": 50, "L0": 5,
                    "burn": 250, "samples": 750, "adapt_length": True,
                    "adapt_mass": bool(adapt_mass)}},
@@ -689,6 +712,11 @@ def main():
                          "distribution (posterior calibration and convergence)")
     ap.add_argument("--recovery-map", type=int, nargs=2, default=[300, 300],
                     metavar=("STARTS", "STEPS"), help="MAP budget of --recovery (Table 1's)")
+    ap.add_argument("--recovery-prior", choices=("paper", "sim"), default="paper",
+                    help="fit prior of --recovery: the paper's broadened one or the simulation "
+                         "distribution")
+    ap.add_argument("--recovery-noise", choices=("poisson", "gauss"), default="poisson",
+                    help="noise of --recovery's images")
     ap.add_argument("--c4-only", action="store_true",
                     help="run only the whole fit of the 60x60 EPL + shapelet system (MAP, VI, "
                          "HMC) and print its JSON")
@@ -726,7 +754,8 @@ def main():
 
     if args.recovery > 0:
         r = recovery_bench(args.recovery, n_map=args.recovery_map[0],
-                           k_map=args.recovery_map[1])
+                           k_map=args.recovery_map[1], prior=args.recovery_prior,
+                           noise=args.recovery_noise)
         print(json.dumps(_finite({"recovery": r}), allow_nan=False), flush=True)
         return
     if args.c4_only:

@@ -292,6 +292,17 @@ def add_noise(clean: np.ndarray, seed: int, sigma_bkg: float, t_exp: float,
     return (shot + rng.normal(0.0, sigma_bkg, size=np.shape(clean))).astype(np.float32)
 
 
+def add_gaussian_noise(clean: np.ndarray, seed: int, sigma_bkg: float, t_exp: float,
+                       gain: float = 1.0) -> np.ndarray:
+    """Observed image whose noise is Gaussian with the variance the likelihood assumes,
+    sigma_bkg^2 + max(I, 0) / (G t_exp): the Poisson shot noise's first two moments
+    without its skewness."""
+    rng = np.random.default_rng(20_000 + seed)
+    c = np.asarray(clean, np.float64)
+    sd = np.sqrt(sigma_bkg ** 2 + np.maximum(c, 0.0) / (gain * t_exp))
+    return (c + rng.normal(size=np.shape(clean)) * sd).astype(np.float32)
+
+
 # ----------------------------------------------------------------------------------------
 # Fit priors (passed to the fit as gl_prior entries). Families and widths follow the
 # paper's broadened prior (blue entries of eq. sim-dist) where its parameter and scale
@@ -302,7 +313,9 @@ def add_noise(clean: np.ndarray, seed: int, sigma_bkg: float, t_exp: float,
 NORMAL, LOGNORMAL, TRUNCNORMAL, UNIFORM = 0, 1, 2, 3
 
 
-def fit_priors(spec: Spec) -> list:
+def fit_priors(spec: Spec, matched: bool = False) -> list:
+    """Per-parameter priors of the fit. matched (only for the paper's distribution): the
+    simulation distribution itself instead of the paper's broadened prior."""
     def N(mu, s):
         return {"family": NORMAL, "mu": mu, "sigma": s, "lo": 0.0, "hi": 0.0}
 
@@ -317,7 +330,9 @@ def fit_priors(spec: Spec) -> list:
 
     if spec.dist == "paper":  # the prior of eq. sim-dist
         out = []
-        for i, (f, _, b) in enumerate(PAPER_DIST):
+        for i, (f, a, b) in enumerate(PAPER_DIST):
+            if matched:
+                b = a
             if f == "ln":
                 out.append(LN(_paper_median(i, b[0], spec.pix), b[1]))
             else:
