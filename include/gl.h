@@ -168,6 +168,14 @@ int gl_loglik_grad_noalloc(gl_model* model, const float* theta, int P, double* l
 int gl_model_stage_times(gl_model* model, const float* theta, int P, int with_grad,
                          double* logl, float* grad, float* ms, void* stream);
 
+/* Diagnostic: as gl_model_stage_times, but n_calls (1 .. 10000) calls back to back on
+ * `stream`, each with its own HIP events (created and destroyed here), one wait after the
+ * last; ms[i] is the mean duration of stage i over the calls. The calls run as a loop of
+ * gl_loglik_grad (or gl_loglik) calls would, so the durations are those of steady-state
+ * launches. GL_E_INVALID for n_calls out of range; the other errors as gl_loglik_grad. */
+int gl_model_stage_times_n(gl_model* model, const float* theta, int P, int with_grad,
+                           int n_calls, double* logl, float* grad, float* ms, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Priors, bijectors and the fixed-budget multi-start fit (Sec. 2.2 bijectors and
  * Jacobian-corrected posterior; Sec. 2.3 multi-start gradient descent with Adam).

@@ -160,16 +160,18 @@ class Model:
 
     STAGES = ("prologue", "subpix_fwd", "conv_lik", "subpix_adj", "finalize")
 
-    def stage_times(self, theta: torch.Tensor, with_grad: bool = True, stream=None) -> dict:
-        """Run the pipeline once with HIP events between its kernels (blocking); returns the
-        milliseconds of each stage."""
+    def stage_times(self, theta: torch.Tensor, with_grad: bool = True, stream=None,
+                    n_calls: int = 1) -> dict:
+        """Run the pipeline n_calls times back to back with HIP events between its kernels
+        (blocking); returns the mean milliseconds of each stage."""
         theta = self._theta(theta)
         P = theta.shape[0]
         ll = torch.empty(P, dtype=torch.float64, device=theta.device)
         g = torch.empty((P, self.d), dtype=torch.float32, device=theta.device)
         ms = (ctypes.c_float * 5)()
-        check(lib().gl_model_stage_times(self._h, theta.data_ptr(), P, int(with_grad),
-                                         ll.data_ptr(), g.data_ptr(), ms, _stream_ptr(stream)))
+        check(lib().gl_model_stage_times_n(self._h, theta.data_ptr(), P, int(with_grad),
+                                           int(n_calls), ll.data_ptr(), g.data_ptr(), ms,
+                                           _stream_ptr(stream)))
         return dict(zip(self.STAGES, list(ms)))
 
 

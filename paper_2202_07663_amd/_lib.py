@@ -113,6 +113,8 @@ _SIGNATURES = {
     "gl_loglik_grad": [_vp, _vp, _i, _vp, _vp, _vp],
     "gl_loglik_grad_noalloc": [_vp, _vp, _i, _vp, _vp, _vp],
     "gl_model_stage_times": [_vp, _vp, _i, _i, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp],
+    "gl_model_stage_times_n": [_vp, _vp, _i, _i, _i, _vp, _vp, ctypes.POINTER(ctypes.c_float),
+                               _vp],
     "gl_fit": [_vp, ctypes.POINTER(FitOpts), ctypes.POINTER(FitResult), _vp],
     "gl_fit_state_create": [_vp, ctypes.POINTER(FitOpts), ctypes.POINTER(_vp), _vp],
     "gl_fit_state_destroy": [_vp],

@@ -703,30 +703,55 @@ int gl_loglik_grad(gl_model* m, const float* theta, int P, double* logl, float* 
   return run_model(m, theta, P, 2, nullptr, logl, grad, (hipStream_t)stream);
 }
 
-int gl_model_stage_times(gl_model* m, const float* theta, int P, int with_grad, double* logl,
-                         float* grad, float* ms, void* stream) {
+int gl_model_stage_times_n(gl_model* m, const float* theta, int P, int with_grad, int n_calls,
+                           double* logl, float* grad, float* ms, void* stream) {
   clear_error();
   int rc = common_checks(m, theta, P);
   if (rc) return rc;
   if (!ms) return set_error(GL_E_INVALID, "ms is NULL");
   for (int i = 0; i < GL_NSTAGES; ++i) ms[i] = 0.f;
+  if (n_calls < 1 || n_calls > kStageTimesMaxCalls)
+    return set_error(GL_E_INVALID, "n_calls must be in [1, %d]", kStageTimesMaxCalls);
   if (P == 0) return GL_OK;
   if (!m->sys.has_obs) return set_error(GL_E_INVALID, "model has no observed image");
   if ((rc = check_device_ptr(logl, "logl"))) return rc;
   if (with_grad && (rc = check_device_ptr(grad, "grad"))) return rc;
-  hipEvent_t ev[GL_NSTAGES + 1];
-  for (auto& e : ev) GL_HIP(hipEventCreate(&e));
+  // one set of events per call, so that the calls run back to back with one wait at the end
+  constexpr int NE = GL_NSTAGES + 1;
+  std::vector<hipEvent_t> ev(size_t(n_calls) * NE, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      rc = set_error(GL_E_DEVICE, "hipEventCreate failed");
+      break;
+    }
   hipStream_t st = (hipStream_t)stream;
-  rc = run_model(m, theta, P, with_grad ? 2 : 1, nullptr, logl, grad, st, ev);
+  for (int c = 0; rc == GL_OK && c < n_calls; ++c)
+    rc = run_model(m, theta, P, with_grad ? 2 : 1, nullptr, logl, grad, st, &ev[size_t(c) * NE]);
+  const int last = with_grad ? GL_NSTAGES : 3;
+  if (rc == GL_OK && hipEventSynchronize(ev[size_t(n_calls - 1) * NE + last]) != hipSuccess)
+    rc = set_error(GL_E_DEVICE, "event sync failed");
   if (rc == GL_OK) {
-    const int last = with_grad ? GL_NSTAGES : 3;
-    if (hipEventSynchronize(ev[last]) != hipSuccess) rc = set_error(GL_E_DEVICE, "event sync failed");
-    for (int i = 0; rc == GL_OK && i < last; ++i)
-      if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess)
-        rc = set_error(GL_E_DEVICE, "event timing failed");
+    double sum[GL_NSTAGES] = {};
+    for (int c = 0; rc == GL_OK && c < n_calls; ++c)
+      for (int i = 0; i < last; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[size_t(c) * NE + i], ev[size_t(c) * NE + i + 1]) !=
+            hipSuccess) {
+          rc = set_error(GL_E_DEVICE, "event timing failed");
+          break;
+        }
+        sum[i] += t;
+      }
+    for (int i = 0; rc == GL_OK && i < last; ++i) ms[i] = float(sum[i] / n_calls);
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
   return rc;
+}
+
+int gl_model_stage_times(gl_model* m, const float* theta, int P, int with_grad, double* logl,
+                         float* grad, float* ms, void* stream) {
+  return gl_model_stage_times_n(m, theta, P, with_grad, 1, logl, grad, ms, stream);
 }
 
 }  // extern "C"

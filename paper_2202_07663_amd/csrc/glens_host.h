@@ -134,6 +134,9 @@ int run_group(Group& g, int key, int K, int mode, hipStream_t st, hipEvent_t* ev
 
 int check_device_ptr(const void* p, const char* name);
 
+// Most calls one gl_model_stage_times_n may time (events per call: GL_NSTAGES + 1).
+constexpr int kStageTimesMaxCalls = 10000;
+
 // Work space of gl_loglik_grad_noalloc: a fixed device array of kNoAllocBytes per device.
 constexpr size_t kNoAllocBytes = size_t(128) << 20;
 size_t noalloc_bytes(const ModelCfg& c, int P);    // its work space at P particles

@@ -316,6 +316,37 @@ def test_host_pointer_rejected(glens):
     assert rc == -1 and b"theta" in _lib.lib().gl_last_error()
 
 
+def test_stage_times_loop(glens):
+    """The stage-timing entry point: n back-to-back calls give the results of gl_loglik_grad
+    (bitwise) and a positive duration for every stage; n out of range is refused."""
+    import ctypes
+    from paper_2202_07663_amd import _lib
+    spec = synth.spec_c1()
+    obs, truth = load_workload(spec.name)
+    theta = synth.draw_particles(spec, truth, 64, seed=4)
+    m = glens.Model.from_spec(spec, obs)
+    ll_ref, g_ref = _run(m, theta)
+    th = torch.from_numpy(theta).cuda()
+    ll = torch.zeros(64, dtype=torch.float64, device="cuda")
+    g = torch.zeros((64, m.d), dtype=torch.float32, device="cuda")
+    ms = (ctypes.c_float * 5)()
+    L = _lib.lib()
+    for bad in (0, 10001):
+        rc = L.gl_model_stage_times_n(m._h, th.data_ptr(), 64, 1, bad, ll.data_ptr(),
+                                      g.data_ptr(), ms, None)
+        assert rc == -1 and b"n_calls" in L.gl_last_error()
+    _say("case stage_times_n sie40 P=64 n=7")
+    check = _lib.check
+    check(L.gl_model_stage_times_n(m._h, th.data_ptr(), 64, 1, 7, ll.data_ptr(), g.data_ptr(),
+                                   ms, None))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ll.cpu().numpy(), ll_ref)
+    np.testing.assert_array_equal(g.cpu().numpy(), g_ref)
+    assert all(t > 0 for t in ms), list(ms)
+    st = m.stage_times(th, with_grad=False, n_calls=3)
+    assert st["subpix_adj"] == 0 and st["finalize"] == 0 and st["subpix_fwd"] > 0
+
+
 def test_repeat_is_bitwise_identical(glens, epl60_case):
     spec, obs, theta = epl60_case
     m = glens.Model.from_spec(spec, obs)
