@@ -713,6 +713,8 @@ def main():
                          "distribution (posterior calibration and convergence)")
     ap.add_argument("--recovery-map", type=int, nargs=2, default=[300, 300],
                     metavar=("STARTS", "STEPS"), help="MAP budget of --recovery (Table 1's)")
+    ap.add_argument("--recovery-seed", type=int, default=1000,
+                    help="seed of --recovery's first system (the others follow)")
     ap.add_argument("--recovery-prior", choices=("paper", "sim"), default="paper",
                     help="fit prior of --recovery: the paper's broadened one or the simulation "
                          "distribution")
@@ -754,7 +756,7 @@ def main():
     import paper_2202_07663_amd as G
 
     if args.recovery > 0:
-        r = recovery_bench(args.recovery, n_map=args.recovery_map[0],
+        r = recovery_bench(args.recovery, seed0=args.recovery_seed, n_map=args.recovery_map[0],
                            k_map=args.recovery_map[1], prior=args.recovery_prior,
                            noise=args.recovery_noise)
         print(json.dumps(_finite({"recovery": r}), allow_nan=False), flush=True)
