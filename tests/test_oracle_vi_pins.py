@@ -127,6 +127,81 @@ def test_gradient_and_loss_on_a_gaussian_target_with_exact_moment_draws():
         assert math.isclose(loss, kl - logZ, rel_tol=1e-12, abs_tol=1e-12)
 
 
+def test_log_q_is_the_normal_density():
+    rng_ = np.random.default_rng(11)
+    d = 5
+    mu = rng_.normal(size=d)
+    v = 0.4 * rng_.normal(size=vi.n_chol(d))
+    L = vi.cholesky_factor(v, d)
+    z = rng_.normal(size=(7, d)) + mu
+    want = stats.multivariate_normal(mean=mu, cov=L @ L.T).logpdf(z)
+    np.testing.assert_allclose(vi.log_q(z, mu, v), want, rtol=1e-12, atol=1e-12)
+
+
+def test_score_matches_finite_differences_of_log_q():
+    """The score of eq. elbo-grad (gradient of log q at fixed z) against central differences
+    of log q in every entry of (mu, v)."""
+    rng_ = np.random.default_rng(12)
+    d = 4
+    mu = rng_.normal(size=d)
+    v = 0.4 * rng_.normal(size=vi.n_chol(d))
+    z = rng_.normal(size=(3, d)) * 1.5 + mu
+    s_mu, s_v = vi.score(z, mu, v)
+    h = 1e-6
+    for q in range(d + vi.n_chol(d)):
+        x = np.concatenate([mu, v])
+        xp, xm = x.copy(), x.copy()
+        xp[q] += h
+        xm[q] -= h
+        fd = (vi.log_q(z, xp[:d], xp[d:]) - vi.log_q(z, xm[:d], xm[d:])) / (2 * h)
+        got = s_mu[:, q] if q < d else s_v[:, q - d]
+        np.testing.assert_allclose(got, fd, rtol=1e-6, atol=1e-7)
+
+
+def test_score_has_zero_mean_under_exact_moment_draws():
+    """E_q[grad log q] = 0: with draws of exactly zero mean and identity second moment the
+    mean score vanishes in every entry."""
+    rng_ = np.random.default_rng(13)
+    d = 4
+    mu = rng_.normal(size=d)
+    v = 0.4 * rng_.normal(size=vi.n_chol(d))
+    L = vi.cholesky_factor(v, d)
+    z = mu[None, :] + _exact_moment_draws(d) @ L.T
+    s_mu, s_v = vi.score(z, mu, v)
+    np.testing.assert_allclose(s_mu.mean(axis=0), 0.0, atol=1e-12)
+    np.testing.assert_allclose(s_v.mean(axis=0), 0.0, atol=1e-12)
+
+
+def test_score_estimator_has_the_pathwise_expectation_on_a_gaussian_target():
+    """Both estimators are unbiased for the same ELBO gradient: on f = (z - c)^T A (z - c)/2
+    the score-function form over many draws lands on the closed form A (mu - c), (A L)_ij,
+    L_ii (A L)_ii - 1 within a few of its standard errors."""
+    rng_ = np.random.default_rng(14)
+    d = 3
+    B = rng_.normal(size=(d, d))
+    A = B @ B.T / d + 0.5 * np.eye(d)
+    c = rng_.normal(size=d)
+    mu = rng_.normal(size=d)
+    v = 0.3 * rng_.normal(size=vi.n_chol(d))
+    L = vi.cholesky_factor(v, d)
+    AL = A @ L
+    want_v = AL.copy()
+    want_v[np.diag_indices(d)] = np.diag(L) * np.diag(AL) - 1.0
+    want = np.concatenate([A @ (mu - c), want_v[np.tril_indices(d)]])
+    eps = rng_.normal(size=(400_000, d))
+    _, g_mu, g_v, n = vi.loss_and_grad_score_fn(_quadratic(A, c), mu, v, eps)
+    assert n == eps.shape[0]
+    got = np.concatenate([g_mu, g_v])
+    # per-draw terms give the standard error of the mean
+    z = mu[None, :] + eps @ L.T
+    f, _ = _quadratic(A, c)(z)
+    w = vi.log_q(z, mu, v) + f
+    s_mu, s_v = vi.score(z, mu, v)
+    terms = w[:, None] * np.concatenate([s_mu, s_v], axis=1)
+    se = terms.std(axis=0) / math.sqrt(n)
+    assert np.all(np.abs(got - want) < 5 * se), (got - want) / se
+
+
 def test_vi_converges_to_a_gaussian_target():
     """On a Gaussian target the optimum of the ELBO is the target itself: mu -> c and
     L L^T -> A^-1 (Adam on random draws: the iterates of the last 1000 steps are averaged
