@@ -268,7 +268,14 @@ typedef struct gl_vi_opts {
   const gl_prior* priors; /* host [d], copied */
   float lr_final;         /* 0: constant after the warm-up; > 0 (with lr_max > 0): the rate
                              on the last iteration, reached geometrically */
+  int estimator;          /* GL_VI_PATHWISE (0, default): the mean of the pathwise terms
+                             (grad f, grad f eps^T); GL_VI_SCORE: the score-function form
+                             of Sec. 2.4's eq. elbo-grad, the mean of
+                             (log q(z) - log p~(I, z)) grad log q(z) at fixed z. Both are
+                             unbiased for the ELBO gradient; the score form uses only the
+                             objective's value and has a far larger variance */
 } gl_vi_opts;
+enum { GL_VI_PATHWISE = 0, GL_VI_SCORE = 1 };
 
 typedef struct gl_vi gl_vi;
 /* Create the state on `model` (with an observed image); mu0: device [d] FP64 (copied). The

@@ -288,17 +288,22 @@ class VI:
     by the library's kernels (one batched likelihood-gradient launch per iteration).
     mu0: [d] start of the mean (the paper: the MAP point, e.g. fit(...)["z_best"]).
     lr_final: 0 keeps lr_max after the warm-up (the paper); > 0 decays the rate geometrically
-    to lr_final on the last iteration."""
+    to lr_final on the last iteration. estimator: "pathwise" (default) or "score" (the
+    score-function form the paper prints, eq. elbo-grad)."""
+
+    ESTIMATORS = {"pathwise": _lib.GL_VI_PATHWISE, "score": _lib.GL_VI_SCORE}
 
     def __init__(self, model: Model, n_samples: int, K: int, priors, mu0, lr_max: float = 1e-3,
                  lr_warmup: int = 500, init_sd: float = 1e-3, seed: int = 0, beta1=0.9,
-                 beta2=0.999, eps=1e-8, lr_final: float = 0.0, stream=None):
+                 beta2=0.999, eps=1e-8, lr_final: float = 0.0, estimator: str = "pathwise",
+                 stream=None):
         assert len(priors) == model.d
         self.model, self.n, self.K, self.d = model, n_samples, K, model.d
         self._pa = make_priors(priors)
         o = _lib.ViOpts(n_samples=n_samples, K=K, lr_max=lr_max, lr_warmup=lr_warmup,
                         beta1=beta1, beta2=beta2, eps=eps, init_sd=init_sd, seed=seed,
-                        priors=self._pa, lr_final=lr_final)
+                        priors=self._pa, lr_final=lr_final,
+                        estimator=self.ESTIMATORS[estimator])
         mu = torch.as_tensor(np.asarray(mu0, np.float64)).reshape(model.d).cuda()
         h = ctypes.c_void_p()
         check(lib().gl_vi_create(model._h, ctypes.byref(o), mu.data_ptr(), ctypes.byref(h),

@@ -74,7 +74,10 @@ class ViOpts(ctypes.Structure):
                 ("lr_warmup", ctypes.c_int), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("init_sd", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("priors", ctypes.POINTER(Prior)), ("lr_final", ctypes.c_float)]
+                ("priors", ctypes.POINTER(Prior)), ("lr_final", ctypes.c_float),
+                ("estimator", ctypes.c_int)]
+
+GL_VI_PATHWISE, GL_VI_SCORE = 0, 1
 
 
 class ServerOpts(ctypes.Structure):

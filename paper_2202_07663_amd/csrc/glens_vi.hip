@@ -20,6 +20,18 @@
 //            then Adam at the iteration's learning rate. x is double-buffered so that every
 //            lane reads the iteration's old state; lane 0 also records the loss
 //            E[f] - sum_i log L_ii - (d/2)(1 + log 2 pi).
+// With the score-function estimator (the form the paper prints, eq. elbo-grad: the mean over
+// the samples of (log q(z) - log p~(I, z)) grad log q(z), grad at fixed z) the last two
+// stages are instead:
+//   reduce   per chunk: w_s = log q(z_s) - log p~(I, z_s) = f_s - |eps_s|^2 / 2
+//            - sum_i log L_ii - (d/2) log 2 pi, and the chunk's sums of w_s eps_s (one per
+//            mu entry) and w_s eps_si eps_sj (i >= j), then its sum of f, count and sum of w;
+//   update   one block: the chunks' sums added in chunk order give a = sum w eps and the
+//            lower triangle of B = sum w eps eps^T; with grad log q = (L^-T eps, the lower
+//            triangle of L^-T eps eps^T, diagonal L_ii (..)_ii - 1) the estimate is
+//            L^-T a / n for mu, (L^-T B)_ij / n for i > j and L_ii (L^-T B)_ii / n -
+//            sum w / n for v_ii; each column of L^-T B is one back substitution with L^T
+//            (rows i >= j only), in LDS; then Adam on every entry.
 // The learning rate rises from 0 to lr_max as lr_max (1 - (1 - k / warmup)^2) over the
 // first `warmup` iterations (the paper: 0 -> 1e-3 over 500), then stays at lr_max, or, when
 // a final rate is given, falls geometrically to it on the last iteration.
@@ -41,6 +53,7 @@ constexpr int kViThreads = 64;
 constexpr int kViChunk = 32;  // samples per block of the reduction
 constexpr uint32_t kViDrawTag = 0x76690000u;
 constexpr uint32_t kViSampleTag = 0x76697371u;
+constexpr double kLog2Pi = 1.8378770664093453;  // log(2 pi)
 
 struct ViArgs {
   int n, d, nc, k;
@@ -199,6 +212,17 @@ __global__ void __launch_bounds__(256) vi_reduce_kernel(ViArgs a) {
   }
 }
 
+// Adam on entry q of x with gradient estimate gq.
+__device__ __forceinline__ void vi_adam_entry(const ViArgs& a, int q, double gq) {
+  const double mq = a.beta1 * a.m[q] + (1.0 - a.beta1) * gq;
+  const double sq = a.beta2 * a.s[q] + (1.0 - a.beta2) * gq * gq;
+  a.m[q] = mq;
+  a.s[q] = sq;
+  const double mhat = mq / a.bc1;
+  const double shat = sq / a.bc2;
+  a.x_new[q] = a.x[q] - a.lr * mhat / (sqrt(shat) + a.adam_eps);
+}
+
 // Gradient estimate and Adam update of one entry of x (and the loss, lane 0), from the
 // chunks' sums.
 __global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a, int chunks) {
@@ -227,15 +251,128 @@ __global__ void __launch_bounds__(256) vi_update_kernel(ViArgs a, int chunks) {
   if (q == 0) {
     double logdet = 0.0;
     for (int t = 0; t < d; ++t) logdet += v[t * (t + 1) / 2 + t];
-    a.loss[a.k] = fsum / nok - logdet - 0.5 * d * (1.0 + 1.8378770664093453);
+    a.loss[a.k] = fsum / nok - logdet - 0.5 * d * (1.0 + kLog2Pi);
   }
-  const double mq = a.beta1 * a.m[q] + (1.0 - a.beta1) * gq;
-  const double sq = a.beta2 * a.s[q] + (1.0 - a.beta2) * gq * gq;
-  a.m[q] = mq;
-  a.s[q] = sq;
-  const double mhat = mq / a.bc1;
-  const double shat = sq / a.bc2;
-  a.x_new[q] = a.x[q] - a.lr * mhat / (sqrt(shat) + a.adam_eps);
+  vi_adam_entry(a, q, gq);
+}
+
+// Score-function estimator, per-chunk sums (one block per kViChunk samples): entry q < d
+// gets sum w eps_q, entry (i, j) of v gets sum w eps_i eps_j; then the chunk's sum of f,
+// count and sum of w. Samples without a finite objective add 0 everywhere.
+__global__ void __launch_bounds__(256) vi_reduce_score_kernel(ViArgs a) {
+  __shared__ double s_e[kViChunk][kMaxParams];
+  __shared__ double s_w[kViChunk];
+  const int d = a.d, nx = a.d + a.nc;
+  const int s0 = blockIdx.x * kViChunk, ns = min(kViChunk, a.n - s0);
+  for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+    const int t = idx / d, j = idx - t * d;
+    s_e[t][j] = a.eps[size_t(s0 + t) * d + j];
+  }
+  __syncthreads();
+  if (threadIdx.x < ns) {
+    const int t = threadIdx.x;
+    const double fs = a.f[s0 + t];
+    double e2 = 0.0, logdet = 0.0;
+    for (int j = 0; j < d; ++j) e2 += s_e[t][j] * s_e[t][j];
+    for (int i = 0; i < d; ++i) logdet += a.x[d + i * (i + 1) / 2 + i];
+    s_w[t] = isfinite(fs) ? fs - 0.5 * e2 - logdet - 0.5 * d * kLog2Pi : 0.0;
+  }
+  __syncthreads();
+  double* out = a.part + size_t(blockIdx.x) * (nx + 3);
+  for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+    int i, j;
+    vi_entry(q, d, i, j);
+    double sum = 0.0;
+    if (j < 0) {
+      for (int t = 0; t < ns; ++t) sum += s_w[t] * s_e[t][i];
+    } else {
+      for (int t = 0; t < ns; ++t) sum += s_w[t] * s_e[t][i] * s_e[t][j];
+    }
+    out[q] = sum;
+  }
+  if (threadIdx.x == 0) {
+    double fsum = 0.0, wsum = 0.0;
+    int nok = 0;
+    for (int t = 0; t < ns; ++t) {
+      const double fs = a.f[s0 + t];
+      if (!isfinite(fs)) continue;
+      ++nok;
+      fsum += fs;
+      wsum += s_w[t];
+    }
+    out[nx] = fsum;
+    out[nx + 1] = nok;
+    out[nx + 2] = wsum;
+  }
+}
+
+// Score-function estimator, one block: chunk sums, the back substitutions with L^T, the
+// estimate and Adam on every entry. Dynamic LDS: L packed [nc] (diagonal exponentiated) and
+// X [d][d + 1]: column j < d holds rows i >= j of B then of L^-T B, column d holds a then
+// L^-T a.
+__global__ void __launch_bounds__(256) vi_update_score_kernel(ViArgs a, int chunks) {
+  extern __shared__ double s_dyn[];
+  __shared__ double s_tot[3];
+  const int d = a.d, nc = a.nc, nx = d + nc, ld = d + 1;
+  double* s_l = s_dyn;
+  double* X = s_dyn + nc;
+  const double* v = a.x + d;
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) s_l[q] = v[q];
+  // chunk sums in chunk order
+  for (int q = threadIdx.x; q < nx + 3; q += blockDim.x) {
+    double sum = 0.0;
+    for (int c = 0; c < chunks; ++c) sum += a.part[size_t(c) * (nx + 3) + q];
+    if (q < d) {
+      X[q * ld + d] = sum;
+    } else if (q < nx) {
+      int i, j;
+      vi_entry(q, d, i, j);
+      X[i * ld + j] = sum;
+    } else {
+      s_tot[q - nx] = sum;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    const int q = i * (i + 1) / 2 + i;
+    s_l[q] = exp(s_l[q]);
+  }
+  __syncthreads();
+  // column t: solve L^T x = b from the last row up (rows >= t for the columns of B)
+  for (int t = threadIdx.x; t <= d; t += blockDim.x) {
+    const int lo = t < d ? t : 0;
+    for (int i = d - 1; i >= lo; --i) {
+      double x = X[i * ld + t];
+      for (int k = i + 1; k < d; ++k) x -= s_l[k * (k + 1) / 2 + i] * X[k * ld + t];
+      X[i * ld + t] = x / s_l[i * (i + 1) / 2 + i];
+    }
+  }
+  __syncthreads();
+  const double fsum = s_tot[0], nokd = s_tot[1], wsum = s_tot[2];
+  const int nok = int(nokd);
+  for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+    if (nok == 0) {  // no usable sample: keep the state
+      a.x_new[q] = a.x[q];
+      if (q == 0) a.loss[a.k] = NAN;
+      continue;
+    }
+    int i, j;
+    vi_entry(q, d, i, j);
+    double gq;
+    if (j < 0) {
+      gq = X[i * ld + d] / nok;
+    } else if (j < i) {
+      gq = X[i * ld + j] / nok;
+    } else {
+      gq = s_l[i * (i + 1) / 2 + i] * X[i * ld + i] / nok - wsum / nok;
+    }
+    if (q == 0) {
+      double logdet = 0.0;
+      for (int t = 0; t < d; ++t) logdet += v[t * (t + 1) / 2 + t];
+      a.loss[a.k] = fsum / nok - logdet - 0.5 * d * (1.0 + kLog2Pi);
+    }
+    vi_adam_entry(a, q, gq);
+  }
 }
 
 // Draws from the surrogate: z_s = mu + L eps_s (FP64), counter (s, j, 0, tag).
@@ -270,6 +407,7 @@ struct gl_vi {
   gl_model* model = nullptr;
   int n = 0, d = 0, nc = 0, K = 0, k = 0, cur = 0, warmup = 0;
   float lr_max = 0.f, lr_final = 0.f;
+  int estimator = GL_VI_PATHWISE;
   char* base = nullptr;
   double* x[2] = {nullptr, nullptr};
   ViArgs a{};
@@ -327,10 +465,18 @@ static int vi_iteration(gl_vi* v, hipStream_t st) {
                      g.sys[0], a);
   if ((rc = vi_check_launch())) return rc;
   const int nx = v->d + v->nc, chunks = (v->n + kViChunk - 1) / kViChunk;
-  hipLaunchKernelGGL(vi_reduce_kernel, dim3(chunks), dim3(256), 0, st, a);
-  if ((rc = vi_check_launch())) return rc;
-  hipLaunchKernelGGL(vi_update_kernel, dim3((nx + 255) / 256), dim3(256), 0, st, a, chunks);
-  if ((rc = vi_check_launch())) return rc;
+  if (v->estimator == GL_VI_SCORE) {
+    const size_t lds = sizeof(double) * (size_t(v->nc) + size_t(v->d) * (v->d + 1));
+    hipLaunchKernelGGL(vi_reduce_score_kernel, dim3(chunks), dim3(256), 0, st, a);
+    if ((rc = vi_check_launch())) return rc;
+    hipLaunchKernelGGL(vi_update_score_kernel, dim3(1), dim3(256), lds, st, a, chunks);
+    if ((rc = vi_check_launch())) return rc;
+  } else {
+    hipLaunchKernelGGL(vi_reduce_kernel, dim3(chunks), dim3(256), 0, st, a);
+    if ((rc = vi_check_launch())) return rc;
+    hipLaunchKernelGGL(vi_update_kernel, dim3((nx + 255) / 256), dim3(256), 0, st, a, chunks);
+    if ((rc = vi_check_launch())) return rc;
+  }
   v->cur = 1 - v->cur;
   v->k++;
   return GL_OK;
@@ -354,6 +500,8 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
     return set_error(GL_E_INVALID, "lr_final must be finite and >= 0 (> 0 needs lr_max > 0)");
   if (!(o->init_sd > 0.f) || !std::isfinite(o->init_sd))
     return set_error(GL_E_INVALID, "init_sd must be > 0");
+  if (o->estimator != GL_VI_PATHWISE && o->estimator != GL_VI_SCORE)
+    return set_error(GL_E_INVALID, "estimator must be GL_VI_PATHWISE or GL_VI_SCORE");
   const ModelCfg& c = m->sys.cfg;
   const int d = c.d, nc = d * (d + 1) / 2, n = o->n_samples, nx = d + nc;
   gl_fit_opts fo;
@@ -375,12 +523,13 @@ int gl_vi_create(gl_model* m, const gl_vi_opts* o, const double* mu0, gl_vi** ou
   v->warmup = o->lr_warmup;
   v->lr_max = o->lr_max;
   v->lr_final = o->lr_final;
+  v->estimator = o->estimator;
   hipStream_t st = (hipStream_t)stream;
   rc = workspace_reserve(m->ws, n, choose_tiles(n, c.H * c.W), c.H * c.W, d, true,
                          beta_per_particle(c));
   if (!rc) rc = fit_buffers_alloc(v->fb, n, d, pri.data());
   const size_t nd = size_t(n) * d;
-  const size_t npart = size_t((n + kViChunk - 1) / kViChunk) * (nx + 2);
+  const size_t npart = size_t((n + kViChunk - 1) / kViChunk) * (nx + 3);
   const size_t bytes = sizeof(double) * (4 * size_t(nx) + nd + n + o->K + npart) +
                        sizeof(float) * 2 * nd + 256 * 12;
   if (!rc && hipMalloc(&v->base, bytes) != hipSuccess) rc = set_error(GL_E_NOMEM, "hipMalloc failed");

@@ -97,6 +97,62 @@ def test_vi_iteration_parity(G, systems, name, k, lr_final):
     np.testing.assert_allclose(st["m"].cpu().numpy(), m_r, rtol=0, atol=2e-3 * scale.max())
 
 
+@pytest.mark.parametrize("name", ["sie40", "vi40"])
+@pytest.mark.parametrize("k", [0, 37, 700])
+def test_vi_score_estimator_iteration_parity(G, systems, name, k):
+    """One iteration with the score-function estimator the paper prints (eq. elbo-grad) on
+    the GPU against the oracle's FP64 iteration with the same Philox draws, at the bar of
+    the pathwise test: warm Adam moments, updates within 0.5% of the learning rate."""
+    spec, obs, priors, fg, z_c, cov = systems[name]
+    d = spec.d
+    n, seed = 48, 91
+    rng = np.random.default_rng(100 + k)
+    L0 = np.linalg.cholesky(cov) * np.exp(0.3 * rng.normal(size=(d, 1)))
+    mu = z_c + 0.5 * np.linalg.cholesky(cov) @ rng.normal(size=d)
+    v = ovi.cholesky_inverse(L0)
+    eps = ovi.draws(seed, d, n, k)
+    _, g_mu, g_v, nok = ovi.loss_and_grad_score_fn(fg, mu, v, eps)
+    assert nok == n
+    g = np.concatenate([g_mu, g_v])
+    scale = np.abs(g) + np.sqrt(np.mean(g ** 2))
+    m0 = g * rng.uniform(-1, 1, g.shape)
+    s0 = scale ** 2 * rng.uniform(1, 2, g.shape)
+    x0 = np.concatenate([mu, v])
+    K = 1000
+    lr = ovi.learning_rate(k, 1e-3, 500, 0.0, K)
+    _say("case vi score", name, "k", k)
+    vi = G.VI(G.Model.from_spec(spec, obs), n, K, priors, mu, lr_max=1e-3, lr_warmup=500,
+              seed=seed, estimator="score")
+    vi.set_state(x0, m0, s0, k)
+    vi.step(1)
+    st = vi.get_state()
+    x_gpu = st["x"].cpu().numpy()
+    loss_gpu = st["loss"].cpu().numpy()[k]
+    mu_r, v_r, m_r, s_r, loss_r = ovi.vi_step(fg, mu, v, m0.copy(), s0.copy(), k, eps, lr,
+                                              estimator="score")
+    x_ref = np.concatenate([mu_r, v_r])
+    dx = np.abs(x_gpu - x_ref)
+    _say(name, k, "lr", lr, "max |dx|/lr", dx.max() / max(lr, 1e-30), "loss", loss_gpu, loss_r)
+    assert st["k"] == k + 1
+    assert dx.max() <= 5e-3 * lr + 1e-12 * np.abs(x_ref).max()
+    assert abs(loss_gpu - loss_r) <= 1e-4 * abs(loss_r)
+    np.testing.assert_allclose(st["m"].cpu().numpy(), m_r, rtol=0, atol=2e-3 * scale.max())
+
+
+def test_vi_estimator_option_is_validated(G, systems):
+    import ctypes
+    from paper_2202_07663_amd import _lib
+    spec, obs, priors, fg, z_c, cov = systems["sie40"]
+    m = G.Model.from_spec(spec, obs)
+    pa = G.make_priors(priors)
+    mu = torch.as_tensor(z_c).cuda()
+    h = ctypes.c_void_p()
+    o = _lib.ViOpts(n_samples=8, K=4, lr_max=1e-3, lr_warmup=2, init_sd=1e-3, seed=1,
+                    priors=pa, estimator=2)
+    rc = _lib.lib().gl_vi_create(m._h, ctypes.byref(o), mu.data_ptr(), ctypes.byref(h), None)
+    assert rc == -1 and b"estimator" in _lib.lib().gl_last_error()
+
+
 def test_surrogate_draws_match_the_oracle_generator(G, systems):
     """gl_vi_sample: z = mu + L eps with eps from Philox counter (draw, parameter, 0, tag);
     the oracle's generator gives the same eps, so the draws agree to rounding."""
