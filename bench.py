@@ -254,6 +254,43 @@ def pipeline_bench(spec, obs, truth, seed=0, n_map=4096, k_map=300, n_vi=1000, k
     }
 
 
+def vi_estimator_bench(seed=1000):
+    """Table 1's VI budget (500 draws x 1000 iterations, rate 0 -> 1e-3 over 500) from the MAP
+    point of one system drawn from the paper's simulation distribution, once with each
+    gradient estimator: seconds, the loss at the start, around iteration 500 and over the
+    last 50 iterations, and the surrogate's standard deviations."""
+    import torch
+    import synth
+    import paper_2202_07663_amd as G
+    sp = synth.spec_paper80()
+    truth = synth.draw_truth(sp, seed)
+    sim = G.Model.from_spec(sp)
+    clean = sim.simulate(torch.from_numpy(truth[None, :]).cuda())[0].cpu().numpy()
+    sim.close()
+    obs = synth.add_noise(clean, seed, sp.sigma_bkg, sp.t_exp)
+    pri = synth.fit_priors(sp)
+    model = G.Model.from_spec(sp, obs)
+    r = G.fit(model, 2048, 2000, pri, seed=seed)
+    out = {"workload": f"paper80 (eq. sim-dist draw, seed {seed}), MAP 2048 x 2000",
+           "map_chi2nu": round(r["chi2nu"], 4)}
+    for est in ("pathwise", "score"):
+        vi = G.VI(model, 500, 1000, pri, r["z_best"].astype(np.float64), lr_max=1e-3,
+                  lr_warmup=500, init_sd=1e-3, seed=seed + 1, estimator=est)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vi.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        loss = vi.get_state()["loss"].cpu().numpy()
+        sd = np.sqrt(np.diag(vi.get()["cov"].cpu().numpy()))
+        out[est] = {"seconds": round(dt, 3), "loss_first": round(float(loss[0]), 2),
+                    "loss_490_510": round(float(np.nanmean(loss[490:510])), 2),
+                    "loss_last50": round(float(np.nanmean(loss[-50:])), 2),
+                    "sd_min": float(sd.min()), "sd_median": float(np.median(sd)),
+                    "sd_max": float(sd.max())}
+    return out
+
+
 def recovery_bench(n_systems, seed0=1000, adapt_mass=True, n_map=300, k_map=300,
                    prior="paper", noise="poisson"):
     """The pipeline at Table 1's sizes on n_systems systems drawn from the paper's simulation
@@ -713,6 +750,9 @@ def main():
                          "distribution (posterior calibration and convergence)")
     ap.add_argument("--recovery-map", type=int, nargs=2, default=[300, 300],
                     metavar=("STARTS", "STEPS"), help="MAP budget of --recovery (Table 1's)")
+    ap.add_argument("--vi-compare", action="store_true",
+                    help="only: Table 1's VI budget with the pathwise and the score-function "
+                         "estimator on one paper80 system")
     ap.add_argument("--recovery-seed", type=int, default=1000,
                     help="seed of --recovery's first system (the others follow)")
     ap.add_argument("--recovery-prior", choices=("paper", "sim"), default="paper",
@@ -755,6 +795,10 @@ def main():
     import torch
     import paper_2202_07663_amd as G
 
+    if args.vi_compare:
+        print(json.dumps(_finite({"vi_estimators": vi_estimator_bench()}), allow_nan=False),
+              flush=True)
+        return
     if args.recovery > 0:
         r = recovery_bench(args.recovery, seed0=args.recovery_seed, n_map=args.recovery_map[0],
                            k_map=args.recovery_map[1], prior=args.recovery_prior,
