@@ -276,9 +276,11 @@ def test_vi_options_and_non_finite_iterations(G, systems):
     with pytest.raises(G.GlError):
         vi.step(1)
     bad = G.Model.from_spec(spec, np.full_like(obs, 1e30))
-    vi = G.VI(bad, 8, 2, priors, z_c, lr_warmup=0)
-    x0 = vi.get_state()["x"].cpu().numpy()
-    vi.step(2)
-    st = vi.get_state()
-    np.testing.assert_array_equal(st["x"].cpu().numpy(), x0)
-    assert np.all(np.isnan(st["loss"].cpu().numpy()))
+    for est in ("pathwise", "score"):
+        _say("case vi non-finite, estimator", est)
+        vi = G.VI(bad, 8, 2, priors, z_c, lr_warmup=0, estimator=est)
+        x0 = vi.get_state()["x"].cpu().numpy()
+        vi.step(2)
+        st = vi.get_state()
+        np.testing.assert_array_equal(st["x"].cpu().numpy(), x0)
+        assert np.all(np.isnan(st["loss"].cpu().numpy()))
