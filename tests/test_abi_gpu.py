@@ -1,8 +1,7 @@
 """C-ABI behaviour on the GPU: compute calls write their outputs only within [P] / [P][d] /
-[P][H][W] and leave their inputs as they were, for batch sizes on every PSF path and ragged
-tile counts; and they are ordered on the stream they are given."""
-import ctypes
-
+[P][H][W] and leave their inputs as they were, for batch sizes on each PSF path (banded,
+matrix cores, whole-image VALU) and ragged tile counts; and they are ordered on the stream
+they are given."""
 import numpy as np
 import pytest
 
@@ -25,15 +24,28 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def _k25_system():
+    """A 40x40 system with a 25x25 PSF (the whole-image VALU PSF kernel at P >= 512); its
+    observed image is a flat 0.1 counts/s (any finite image serves here)."""
+    spec = synth.spec_custom(40, 1, epl=True, lens_light=True, nmax=2, K=25)
+    return spec, np.full((spec.H, spec.W), 0.1, np.float32), synth.draw_truth(spec, 0)
+
+
 @pytest.mark.parametrize("spec_fn,P", [(synth.spec_c1, 1), (synth.spec_c1, 65),
-                                       (synth.spec_c2, 63), (synth.spec_c2, 513)])
+                                       (synth.spec_c2, 63), (synth.spec_c2, 513),
+                                       ("k25", 512)])
 def test_outputs_stay_within_their_extent(G, spec_fn, P):
     from paper_2202_07663_amd import _lib
-    spec = spec_fn()
-    obs, truth = load_workload(spec.name)
+    if spec_fn == "k25":
+        spec, obs, truth = _k25_system()
+    else:
+        spec = spec_fn()
+        obs, truth = load_workload(spec.name)
     m = G.Model.from_spec(spec, obs)
     d, H, W = m.d, spec.H, spec.W
-    _say("case extent", spec.name, "P", P, "psf path", m.plan(P)["psf_path"])
+    path = m.plan(P)["psf_path"]
+    _say("case extent", spec.name, "P", P, "psf path", path)
+    assert path == {1: "banded", 63: "banded", 65: "banded", 513: "mfma", 512: "valu"}[P]
     theta = torch.from_numpy(synth.draw_particles(spec, truth, P, seed=3)).cuda()
     theta_before = theta.clone()
     pad = 3
